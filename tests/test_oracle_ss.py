@@ -1,0 +1,99 @@
+"""Pins of the oracle's Sakurai-Sugiura steps (paper Sec. 3, Algorithm 1).
+
+* quadrature: for the scalar P(z) = z - a the trapezoid moments on the ring
+  equal a^k F(a) with F(a) = 1/(1+(a/rho1)^N) - 1/(1+(a/rho2)^N) for k < N,
+  a closed form obtained by expanding 1/(z - a) in a geometric series (the
+  shifted nodes satisfy z_j^N = -rho^N);
+* brute force: a diagonal QEP whose roots are known in closed form;
+* the whole dense SS pipeline against QZ on the smallest configuration;
+* BiCG and its dual against a dense LU solve.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ham, qep, ss
+
+
+@pytest.mark.parametrize("a", [0.3, 0.9 + 0.2j, -1.5j, 1.9, 2.6, 0.7 * np.exp(2j)])
+def test_quadrature_filter_closed_form(a):
+    lmin, N = 0.5, 32
+    z1, w1, z2, w2 = ss.quadrature(lmin, N)
+    rho1, rho2 = 1 / lmin, lmin
+    F = 1 / (1 + (a / rho1) ** N) - 1 / (1 + (a / rho2) ** N)
+    for k in range(0, N):
+        sk = np.sum(w1 * z1 ** k / (z1 - a)) - np.sum(w2 * z2 ** k / (z2 - a))
+        # rounding of a sum whose largest terms are ~ rho1^k
+        assert abs(sk - a ** k * F) <= 1e-13 + 1e-15 * N * rho1 ** k
+
+
+def test_quadrature_nodes():
+    z1, w1, z2, w2 = ss.quadrature(0.5, 32)
+    np.testing.assert_allclose(np.abs(z1), 2.0)
+    np.testing.assert_allclose(np.abs(z2), 0.5)
+    np.testing.assert_allclose(z2, 1 / np.conj(z1), rtol=1e-15)
+    np.testing.assert_allclose(z1 ** 32, -(2.0 ** 32), rtol=1e-12)
+
+
+class _Diag:
+    """A decoupled QEP: every diagonal entry is a scalar quadratic."""
+
+    def __init__(self, d0, dp):
+        self.h0, self.hp = np.diag(d0), np.diag(dp)
+
+    def blocks_dense(self):
+        return self.h0, self.hp, self.hp.T
+
+
+def test_ss_diagonal_qep_brute_force():
+    rng = np.random.default_rng(11)
+    n = 40
+    d0 = rng.uniform(-3, 3, n)
+    dp = rng.uniform(0.5, 1.5, n)
+    E = 0.2
+    # roots of (d0 - E) + lam dp + dp / lam = 0
+    b = d0 - E
+    roots = np.concatenate([(-b + np.sqrt(b * b - 4 * dp * dp + 0j)) / (2 * dp),
+                            (-b - np.sqrt(b * b - 4 * dp * dp + 0j)) / (2 * dp)])
+    want = qep.in_annulus(roots, 0.5)
+    # keep away from the contour so the filter does not matter
+    assert np.min(np.abs(np.abs(np.log(np.abs(roots))) - np.log(2))) > 0.05
+    V = W.make_rhs(n, 8, 5)
+    r = ss.ss_dense(_Diag(d0, dp), E, V, 0.5, 32, 8)
+    got = qep.in_annulus(r.lam_rr, 0.5)
+    assert len(got) == len(want) > 4
+    assert qep.match_sets(got, want) < 1e-10
+
+
+@pytest.fixture(scope="module")
+def cfg1_e1():
+    s = W.config(1).systems[0]
+    H = ham.build(s)
+    h0, hp, hm = H.blocks_dense()
+    return H, qep.solve_dense(h0, hp, hm, 1.0, 0.5, left=False)
+
+
+def test_ss_matches_qz_cfg1(cfg1_e1):
+    H, ref = cfg1_e1
+    V = W.make_rhs(H.n, 8, 3001)
+    r = ss.ss_dense(H, 1.0, V, 0.5, 32, 8)
+    assert r.rank < 64
+    assert qep.match_sets(qep.in_annulus(r.lam_rr, 0.5), ref.lam) < 1e-10
+    assert qep.match_sets(qep.in_annulus(r.lam_hankel, 0.5), ref.lam) < 1e-6
+    # lambda does not depend on the random block V
+    r2 = ss.ss_dense(H, 1.0, W.make_rhs(H.n, 8, 999), 0.5, 32, 8)
+    assert qep.match_sets(qep.in_annulus(r2.lam_rr, 0.5), ref.lam) < 1e-10
+
+
+def test_bicg_primal_and_dual_match_lu():
+    s = W.tiny(with_proj=True, fd_order=8)
+    H = ham.build(s)
+    h0, hp, hm = H.blocks_dense()
+    z1, _, z2, _ = ss.quadrature(0.5, 32)
+    v = W.make_rhs(s.n, 1, 3)[0]
+    for j in (0, 7, 20):
+        x, xt, it, rr, rrt = ss.bicg(lambda u: H.apply(z1[j], u, 0.7),
+                                     lambda u: H.apply(1 / np.conj(z1[j]), u, 0.7), v, v)
+        assert rr < 1e-10 and rrt < 1e-10
+        np.testing.assert_allclose(x, np.linalg.solve(qep.P_dense(h0, hp, hm, 0.7, z1[j]), v), atol=1e-8)
+        np.testing.assert_allclose(xt, np.linalg.solve(qep.P_dense(h0, hp, hm, 0.7, z2[j]), v), atol=1e-8)
