@@ -1,0 +1,207 @@
+/*
+ * cbs.h - C ABI of the MI355X Sakurai-Sugiura complex-band-structure library.
+ *
+ * The library computes, at a real energy E, the Bloch factors lambda with
+ * lambda_min < |lambda| < 1/lambda_min of the quadratic eigenvalue problem
+ * (Iwase et al., SC17, Sec. 2, Eqs. 4-5)
+ *
+ *     P(lambda) psi = [ (H0 - E) + lambda H+ + lambda^{-1} H- ] psi = 0,
+ *
+ * where H0, H+ and H- = H+^T are the cell blocks of a real-space
+ * finite-difference Kohn-Sham Hamiltonian: -1/2 Laplacian by central finite
+ * differences of order fd_order (x, y periodic with phase 1, z coupled to the
+ * neighbouring cells), a local potential V_loc on the diagonal, and separable
+ * nonlocal projectors V_nl = sum_{a,i} h_ai |u_ai><u_ai| summed over the
+ * periodic images of each atom.  (P is the negative of the paper's Eq. 4
+ * operator; the eigenpairs are the same.)
+ *
+ * Method (paper Sec. 3): BiCG solves of P(z_j) Y_j = V at the trapezoid
+ * nodes z_j of the outer circle, whose dual systems P(z_j)^H Yt_j = V are the
+ * inner-circle solves because P(z)^H = P(1/conj z) (Sec. 3.2, Eq. 11); the
+ * moments S_k = sum_j w_j z_j^k Y_j over the ring contour (Sec. 3.2, Eq. 7);
+ * block Hankel matrices of mu_k = V^H S_k, their truncated SVD and the
+ * reduced eigenproblem (Sec. 3.1, Algorithm 1); optionally a Rayleigh-Ritz
+ * projection of the QEP onto the span of the Hankel Ritz vectors.
+ *
+ * Conventions
+ *   - Complex numbers are interleaved (re, im) pairs of double (complex128)
+ *     or float (complex64).
+ *   - Grid point index n = ix + nx*(iy + ny*iz), N = nx*ny*nz.
+ *   - A block of k vectors of length N is stored vector-major: element
+ *     (vector v, point n) at offset v*N + n (in complex elements).
+ *   - "device" pointers are HIP device memory on the system's device, owned
+ *     by the caller; "host" pointers are ordinary host memory, owned by the
+ *     caller.  No call keeps a caller pointer after it returns.
+ *   - stream: a hipStream_t (NULL = the default stream).  Calls that return
+ *     host results synchronise that stream before returning.
+ *   - Every function returns CBS_OK (0) or a negative error code; on error no
+ *     output is guaranteed except where stated.  cbs_strerror() names codes,
+ *     cbs_last_error() gives a message for the last failure on this thread.
+ */
+#ifndef CBS_H
+#define CBS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CBS_OK = 0,
+  CBS_EINVAL = -1,      /* bad argument or unsupported shape */
+  CBS_ENOMEM = -2,      /* device allocation failed */
+  CBS_EHIP = -3,        /* HIP runtime error */
+  CBS_ENOCONV = -4,     /* a linear solve missed its tolerance (results written) */
+  CBS_EBREAKDOWN = -5,  /* BiCG breakdown (zero rho or sigma) */
+  CBS_ERANK = -6,       /* Hankel rank reached L*M: subspace too small (results written) */
+  CBS_ETOOMANY = -7     /* more eigenvalues than max_eigs (count written) */
+};
+
+enum { CBS_C128 = 0, CBS_C64 = 1 };          /* element type of cbs_apply vectors */
+enum { CBS_FP64 = 0, CBS_MIXED = 1 };        /* solve precision */
+enum { CBS_RR = 0, CBS_HANKEL = 1 };         /* eigenpair extraction */
+
+typedef struct cbs_system cbs_system;
+
+/* Grid of one periodic cell.  fd_order in {2, 4, 6, 8} (half-width p = fd_order/2);
+ * requires nz >= p, 1 <= nx <= 256, ny >= 1, h > 0. */
+typedef struct {
+  int32_t nx, ny, nz, fd_order;
+  double h;
+} cbs_grid;
+
+/* Separable nonlocal projectors (paper Sec. 4: norm-conserving pseudopotentials),
+ * host arrays, CSR over atoms.  Ball entry e of atom a (ball_off[a] <= e <
+ * ball_off[a+1]) sits at cell point ball_idx[e] of the cell shifted by
+ * ball_w[e] in {-1, 0, 1} along z, and carries the values ball_val[e*n_proj + i]
+ * of the atom's n_proj (<= 4) projectors (grid-normalised u = h^{3/2} p).
+ * coeff[a*n_proj + i] is h_ai.  Each atom's entries must span at most two
+ * adjacent shifts (projector diameter below the cell length), so that only
+ * nearest cells couple. */
+typedef struct {
+  int32_t n_atoms, n_proj;
+  const int64_t* ball_off;   /* [n_atoms+1] */
+  const int32_t* ball_idx;   /* [nnz] */
+  const int8_t* ball_w;      /* [nnz] */
+  const double* ball_val;    /* [nnz*n_proj] */
+  const double* coeff;       /* [n_atoms*n_proj] */
+} cbs_proj;
+
+/* Contour and solver parameters (paper Sec. 3 and 4.1; defaults from
+ * cbs_params_default: lambda_min 0.5, n_q 32, n_rhs 16, n_mom 8, delta 1e-10,
+ * tol 1e-10). */
+typedef struct {
+  double lambda_min;    /* annulus lambda_min < |lambda| < 1/lambda_min, 0 < lambda_min < 1 */
+  int32_t n_q;          /* trapezoid nodes per circle (N_int) */
+  int32_t n_rhs;        /* right-hand sides L (N_rh) */
+  int32_t n_mom;        /* moments M (N_mm); Hankel size L*M <= 256; 2*M <= n_q */
+  double delta;         /* SVD rank threshold, relative to the largest singular value */
+  double tol;           /* per-column relative residual of every solve (primal and dual) */
+  int32_t max_iter;     /* BiCG iteration cap (per inner solve) */
+  int32_t precision;    /* CBS_FP64 or CBS_MIXED (complex64 BiCG + FP64 refinement) */
+  int32_t extraction;   /* CBS_RR (default) or CBS_HANKEL */
+  int32_t half_stop;    /* 1: stop all solves once more than half of the nodes converged (Sec. 3.3) */
+  double inner_tol;     /* CBS_MIXED: relative tolerance of each complex64 inner solve */
+  int32_t max_refine;   /* CBS_MIXED: cap on FP64 refinement steps */
+  int32_t chunk;        /* iterations per captured graph between convergence polls (even) */
+} cbs_params;
+
+/* Per-solve diagnostics. */
+typedef struct {
+  int32_t rank;             /* numerical rank m of the Hankel matrix */
+  int32_t n_eigs;           /* eigenpairs returned (inside the annulus) */
+  int32_t iters_max;        /* largest BiCG iteration count over all runs (summed over refinement) */
+  int32_t refine_steps;     /* FP64 refinement steps (CBS_MIXED) */
+  double iters_mean;        /* mean BiCG iterations per run */
+  double max_solve_resid;   /* max over all solves of ||v - P(z)y|| / ||v|| (recursive, or FP64 recomputed for CBS_MIXED) */
+  double max_eig_resid;     /* max ||P(lambda) psi|| / ||psi|| over returned pairs */
+  double sigma_first;       /* largest singular value of the Hankel matrix */
+  double sigma_ratio;       /* sigma_m / sigma_1 of the last kept singular value */
+  double t_solve_ms, t_moments_ms, t_extract_ms;   /* wall time of the three steps */
+  int64_t matvecs;          /* operator applications (vectors) in the solves */
+} cbs_info;
+
+/* ---- errors ---------------------------------------------------------- */
+const char* cbs_strerror(int32_t code);
+const char* cbs_last_error(void);
+
+/* ---- systems (paper Sec. 2: the cell blocks of one crystal) ---------- */
+
+/* Uploads the grid, local potential (host [N] double) and projector tables
+ * (host, may be NULL) to `device` and builds the point-major projector index.
+ * Not timed in a solve.  Errors: CBS_EINVAL (shape), CBS_ENOMEM, CBS_EHIP. */
+int32_t cbs_system_create(cbs_system** out, int32_t device, const cbs_grid* grid,
+                          const double* v_loc, const cbs_proj* proj);
+void cbs_system_destroy(cbs_system* sys);
+/* Replace V_loc (host [N] double); keeps projectors and workspace. */
+int32_t cbs_system_set_vloc(cbs_system* sys, const double* v_loc);
+int64_t cbs_system_npoints(const cbs_system* sys);
+
+void cbs_params_default(cbs_params* p);
+
+/* ---- operator (Eq. 4) --------------------------------------------------
+ * y_v = P(z_v) x_v for a batch of n_vec vectors (device, [n_vec][N], dtype
+ * CBS_C128 or CBS_C64), z host [2*n_vec] (re, im), z_v != 0.  x and y must not
+ * overlap.  complex64 runs the single-precision kernels end to end. */
+int32_t cbs_apply(cbs_system* sys, double E, int32_t n_vec, const double* z,
+                  int32_t dtype, const void* x, void* y, void* stream);
+
+/* y_v = c0_v (H0 - E) x_v + cp_v H+ x_v + cm_v H- x_v, coefficients host
+ * [2*n_vec] each (re, im); complex128 only.  The z-split form of cbs_apply,
+ * used for Rayleigh-Ritz projections. */
+int32_t cbs_apply_parts(cbs_system* sys, double E, int32_t n_vec, const double* c0,
+                        const double* cp, const double* cm, const void* x, void* y,
+                        void* stream);
+
+/* ---- step 1: BiCG with duals (Sec. 3.2, Eqs. 9-11) ---------------------
+ * For every node z_j (host [2*n_z]) and right-hand side v_l (device [L][N]
+ * complex128) solves P(z_j) y = v_l and, as the BiCG dual, P(z_j)^H yt = v_l,
+ * to params->tol (precision CBS_FP64 or CBS_MIXED as in cbs_solve).  Y, Yt
+ * device [n_z][L][N] complex128.  iters (host [n_z*L], may be NULL) receives
+ * the iteration count of each run and relres (host [2*n_z*L], may be NULL) the
+ * final relative residuals (primal, dual).  Returns CBS_ENOCONV if a run
+ * missed tol within max_iter (results still written). */
+int32_t cbs_bicg(cbs_system* sys, double E, int32_t n_z, const double* z, int32_t n_rhs,
+                 const void* V, const cbs_params* params, void* Y, void* Yt,
+                 int32_t* iters, double* relres, cbs_info* info, void* stream);
+
+/* ---- the whole method at one energy (Algorithm 1 on the ring contour) --
+ * V: device [L][N] complex128 right-hand sides (L = params->n_rhs).
+ * lambda: host [2*max_eigs], resid: host [max_eigs] (may be NULL),
+ * vecs: device [max_eigs][N] complex128 (may be NULL), unit 2-norm, largest
+ * component real positive.  Eigenvalues are sorted by |ln|lambda||, then by
+ * arg lambda.  Returns CBS_ETOOMANY with *n_eigs = needed count when
+ * max_eigs is too small; CBS_ERANK when the Hankel rank equals L*M (results
+ * written, subspace too small); CBS_ENOCONV when a solve missed tol (results
+ * written).  The last solve's eigenpairs stay on the system for
+ * cbs_grad_vloc. */
+int32_t cbs_solve(cbs_system* sys, double E, const cbs_params* params, const void* V,
+                  int32_t max_eigs, double* lambda, double* resid, void* vecs,
+                  int32_t* n_eigs, cbs_info* info, void* stream);
+
+/* ---- batching: energies x systems in one pass ------------------------
+ * Solves every (system s, energy e) pair with the same parameters.  All
+ * quadrature nodes, right-hand sides, energies and systems share each BiCG
+ * kernel launch.  V[s]: device [L][N_s] complex128.  lambda: host
+ * [n_sys][n_E][2*max_eigs]; n_eigs: host [n_sys*n_E]; info: host [n_sys*n_E]
+ * (may be NULL).  Error codes as cbs_solve (the worst over all pairs). */
+int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, int32_t n_E,
+                          const double* E, const cbs_params* params,
+                          const void* const* V, int32_t max_eigs, double* lambda,
+                          int32_t* n_eigs, cbs_info* info, void* stream);
+
+/* ---- adjoint --------------------------------------------------------
+ * d lambda_i / d V_loc(r) for eigenpairs sel[k] (indices into the last
+ * cbs_solve's output) = -conj(y_i(r)) x_i(r) / (y_i^H P'(lambda_i) x_i) with
+ * P'(lambda) = H+ - lambda^{-2} H- and y_i the eigenvector of the pair
+ * partner 1/conj(lambda_i) (P(lambda)^H = P(1/conj lambda), Sec. 3.2).
+ * out: device [n_sel][N] complex128.  CBS_EINVAL if no solve is stored, an
+ * index is out of range, or a selected eigenvalue has no simple partner. */
+int32_t cbs_grad_vloc(cbs_system* sys, int32_t n_sel, const int32_t* sel, void* out,
+                      void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CBS_H */

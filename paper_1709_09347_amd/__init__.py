@@ -1,0 +1,295 @@
+"""MI355X Sakurai-Sugiura complex-band-structure library: Python binding.
+
+A thin ctypes layer over ``libcbs.so`` (the C ABI in ``include/cbs.h``).  It
+only marshals arguments: every step of the method runs in the library's HIP
+kernels.  PyTorch provides device memory (tensors passed by ``data_ptr()``)
+and streams (``torch.cuda.current_stream()``).  If the library is not built,
+every call raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcbs.so")
+
+CBS_OK, CBS_EINVAL, CBS_ENOMEM, CBS_EHIP, CBS_ENOCONV, CBS_EBREAKDOWN, CBS_ERANK, CBS_ETOOMANY = \
+    0, -1, -2, -3, -4, -5, -6, -7
+CBS_C128, CBS_C64 = 0, 1
+CBS_FP64, CBS_MIXED = 0, 1
+CBS_RR, CBS_HANKEL = 0, 1
+
+# every function the header declares
+EXPORTS = [
+    "cbs_strerror", "cbs_last_error", "cbs_system_create", "cbs_system_destroy",
+    "cbs_system_set_vloc", "cbs_system_npoints", "cbs_params_default", "cbs_apply",
+    "cbs_apply_parts", "cbs_bicg", "cbs_solve", "cbs_solve_batched", "cbs_grad_vloc",
+]
+
+
+class CbsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("fd_order", ctypes.c_int32), ("h", ctypes.c_double)]
+
+
+class Proj(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("n_proj", ctypes.c_int32),
+                ("ball_off", ctypes.c_void_p), ("ball_idx", ctypes.c_void_p),
+                ("ball_w", ctypes.c_void_p), ("ball_val", ctypes.c_void_p),
+                ("coeff", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lambda_min", ctypes.c_double), ("n_q", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
+                ("n_mom", ctypes.c_int32), ("delta", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("extraction", ctypes.c_int32), ("half_stop", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
+                ("chunk", ctypes.c_int32)]
+
+    def __repr__(self):
+        return "Params(" + ", ".join(f"{n}={getattr(self, n)}" for n, _ in self._fields_) + ")"
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("n_eigs", ctypes.c_int32), ("iters_max", ctypes.c_int32),
+                ("refine_steps", ctypes.c_int32), ("iters_mean", ctypes.c_double),
+                ("max_solve_resid", ctypes.c_double), ("max_eig_resid", ctypes.c_double),
+                ("sigma_first", ctypes.c_double), ("sigma_ratio", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("t_moments_ms", ctypes.c_double),
+                ("t_extract_ms", ctypes.c_double), ("matvecs", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_LIB = None
+
+
+def lib():
+    """Load libcbs.so (raises if it is not built: the HIP path is the only path)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.cbs_strerror.restype = ctypes.c_char_p
+        L.cbs_strerror.argtypes = [i32]
+        L.cbs_last_error.restype = ctypes.c_char_p
+        L.cbs_last_error.argtypes = []
+        L.cbs_system_create.restype = i32
+        L.cbs_system_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Grid), vp,
+                                        ctypes.POINTER(Proj)]
+        L.cbs_system_destroy.restype = None
+        L.cbs_system_destroy.argtypes = [vp]
+        L.cbs_system_set_vloc.restype = i32
+        L.cbs_system_set_vloc.argtypes = [vp, vp]
+        L.cbs_system_npoints.restype = i64
+        L.cbs_system_npoints.argtypes = [vp]
+        L.cbs_params_default.restype = None
+        L.cbs_params_default.argtypes = [ctypes.POINTER(Params)]
+        L.cbs_apply.restype = i32
+        L.cbs_apply.argtypes = [vp, dbl, i32, vp, i32, vp, vp, vp]
+        L.cbs_apply_parts.restype = i32
+        L.cbs_apply_parts.argtypes = [vp, dbl, i32, vp, vp, vp, vp, vp, vp]
+        L.cbs_bicg.restype = i32
+        L.cbs_bicg.argtypes = [vp, dbl, i32, vp, i32, vp, ctypes.POINTER(Params), vp, vp, vp, vp,
+                               ctypes.POINTER(Info), vp]
+        L.cbs_solve.restype = i32
+        L.cbs_solve.argtypes = [vp, dbl, ctypes.POINTER(Params), vp, i32, vp, vp, vp,
+                                ctypes.POINTER(i32), ctypes.POINTER(Info), vp]
+        L.cbs_solve_batched.restype = i32
+        L.cbs_solve_batched.argtypes = [i32, vp, i32, vp, ctypes.POINTER(Params), vp, i32, vp, vp,
+                                        vp, vp]
+        L.cbs_grad_vloc.restype = i32
+        L.cbs_grad_vloc.argtypes = [vp, i32, vp, vp, vp]
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int, what: str, ok=(CBS_OK,)):
+    if rc not in ok:
+        L = lib()
+        raise CbsError(rc, f"{what}: {L.cbs_strerror(rc).decode()}: {L.cbs_last_error().decode()}")
+    return rc
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().cbs_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _host_c128(z) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+
+
+class System:
+    """One periodic cell on one device (wraps cbs_system)."""
+
+    def __init__(self, nx, ny, nz, h, fd_order, v_loc, proj=None, device: int = 0):
+        L = lib()
+        self._keep = []
+        g = Grid(nx, ny, nz, fd_order, h)
+        v = np.ascontiguousarray(np.asarray(v_loc, dtype=np.float64))
+        if v.size != nx * ny * nz:
+            raise ValueError("v_loc has the wrong length")
+        pr = None
+        if proj is not None and proj.n_atoms > 0:
+            arrs = [np.ascontiguousarray(proj.ball_off, dtype=np.int64),
+                    np.ascontiguousarray(proj.ball_idx, dtype=np.int32),
+                    np.ascontiguousarray(proj.ball_w, dtype=np.int8),
+                    np.ascontiguousarray(proj.ball_val, dtype=np.float64),
+                    np.ascontiguousarray(proj.coeff, dtype=np.float64)]
+            self._keep = arrs
+            pr = Proj(proj.n_atoms, proj.n_proj, *[a.ctypes.data for a in arrs])
+        h_ = ctypes.c_void_p()
+        _check(L.cbs_system_create(ctypes.byref(h_), device, ctypes.byref(g), v.ctypes.data,
+                                   ctypes.byref(pr) if pr is not None else None),
+               "cbs_system_create")
+        self.handle = h_
+        self.n = nx * ny * nz
+        self.shape = (nx, ny, nz)
+        self.device = device
+        self._keep = []
+
+    @classmethod
+    def from_workload(cls, sys, device: int = 0):
+        return cls(sys.nx, sys.ny, sys.nz, sys.h, sys.fd_order, sys.v_loc, sys.proj, device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cbs_system_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_vloc(self, v_loc):
+        v = np.ascontiguousarray(np.asarray(v_loc, dtype=np.float64))
+        _check(lib().cbs_system_set_vloc(self.handle, v.ctypes.data), "cbs_system_set_vloc")
+
+    # ---- operator -----------------------------------------------------------
+    def apply(self, E: float, z, x, y=None, stream=None):
+        """y_v = P(z_v) x_v; x a [n_vec, N] complex128/complex64 CUDA tensor."""
+        import torch
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        zz = _host_c128(z)
+        nv = x.shape[0]
+        if zz.size != nv:
+            raise ValueError("one z per vector")
+        dt = {torch.complex128: CBS_C128, torch.complex64: CBS_C64}[x.dtype]
+        _check(lib().cbs_apply(self.handle, float(E), nv, zz.ctypes.data, dt, _ptr(x), _ptr(y),
+                               _stream(stream)), "cbs_apply")
+        return y
+
+    def apply_parts(self, E: float, c0, cp, cm, x, y=None, stream=None):
+        import torch
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        a, b, c = _host_c128(c0), _host_c128(cp), _host_c128(cm)
+        _check(lib().cbs_apply_parts(self.handle, float(E), x.shape[0], a.ctypes.data,
+                                     b.ctypes.data, c.ctypes.data, _ptr(x), _ptr(y),
+                                     _stream(stream)), "cbs_apply_parts")
+        return y
+
+    # ---- step 1 ------------------------------------------------------------
+    def bicg(self, E: float, z, V, params: Optional[Params] = None, stream=None):
+        """Solve P(z_j) Y = V and P(z_j)^H Yt = V for every node; returns (Y, Yt, iters, relres, info)."""
+        import torch
+        params = params or default_params()
+        V = V.contiguous()
+        L_, N = V.shape
+        zz = _host_c128(z)
+        nz = zz.size
+        Y = torch.empty((nz, L_, N), dtype=torch.complex128, device=V.device)
+        Yt = torch.empty_like(Y)
+        iters = np.zeros(nz * L_, dtype=np.int32)
+        relres = np.zeros(2 * nz * L_, dtype=np.float64)
+        info = Info()
+        rc = lib().cbs_bicg(self.handle, float(E), nz, zz.ctypes.data, L_, _ptr(V),
+                            ctypes.byref(params), _ptr(Y), _ptr(Yt), iters.ctypes.data,
+                            relres.ctypes.data, ctypes.byref(info), _stream(stream))
+        _check(rc, "cbs_bicg", ok=(CBS_OK, CBS_ENOCONV))
+        return Y, Yt, iters.reshape(nz, L_), relres.reshape(nz, L_, 2), info, rc
+
+    # ---- the whole method ----------------------------------------------------
+    def solve(self, E: float, V, params: Optional[Params] = None, max_eigs: int = 512,
+              want_vectors: bool = True, stream=None):
+        """Eigenpairs inside the annulus; returns (lam [m] complex128 numpy, vecs [m, N] tensor|None,
+        resid [m], info, rc)."""
+        import torch
+        params = params or default_params()
+        V = V.contiguous()
+        lam = np.zeros(2 * max_eigs, dtype=np.float64)
+        res = np.zeros(max_eigs, dtype=np.float64)
+        vecs = torch.empty((max_eigs, self.n), dtype=torch.complex128, device=V.device) \
+            if want_vectors else None
+        n = ctypes.c_int32(0)
+        info = Info()
+        rc = lib().cbs_solve(self.handle, float(E), ctypes.byref(params), _ptr(V), max_eigs,
+                             lam.ctypes.data, res.ctypes.data,
+                             _ptr(vecs) if vecs is not None else None, ctypes.byref(n),
+                             ctypes.byref(info), _stream(stream))
+        _check(rc, "cbs_solve", ok=(CBS_OK, CBS_ENOCONV, CBS_ERANK))
+        m = n.value
+        lamc = lam[:2 * m].view(np.complex128).copy()
+        return lamc, (vecs[:m] if vecs is not None else None), res[:m].copy(), info, rc
+
+    def grad_vloc(self, sel: Sequence[int], stream=None):
+        import torch
+        s = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
+        out = torch.empty((len(s), self.n), dtype=torch.complex128, device=f"cuda:{self.device}")
+        _check(lib().cbs_grad_vloc(self.handle, len(s), s.ctypes.data, _ptr(out), _stream(stream)),
+               "cbs_grad_vloc")
+        return out
+
+
+def solve_batched(systems: List[System], energies, Vs, params: Optional[Params] = None,
+                  max_eigs: int = 512, stream=None):
+    """Every (system, energy) pair in one batched pass; returns (lam list-of-lists, infos, rc)."""
+    params = params or default_params()
+    ns, ne = len(systems), len(energies)
+    handles = (ctypes.c_void_p * ns)(*[s.handle for s in systems])
+    vps = (ctypes.c_void_p * ns)(*[v.data_ptr() for v in Vs])
+    E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64))
+    lam = np.zeros((ns, ne, 2 * max_eigs), dtype=np.float64)
+    cnt = np.zeros(ns * ne, dtype=np.int32)
+    infos = (Info * (ns * ne))()
+    rc = lib().cbs_solve_batched(ns, handles, ne, E.ctypes.data, ctypes.byref(params), vps,
+                                 max_eigs, lam.ctypes.data, cnt.ctypes.data, infos, _stream(stream))
+    _check(rc, "cbs_solve_batched", ok=(CBS_OK, CBS_ENOCONV, CBS_ERANK))
+    out = [[lam[s, e, :2 * cnt[s * ne + e]].view(np.complex128).copy() for e in range(ne)]
+           for s in range(ns)]
+    return out, [infos[i] for i in range(ns * ne)], rc

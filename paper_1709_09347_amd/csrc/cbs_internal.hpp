@@ -1,0 +1,226 @@
+// Internal declarations of the MI355X Sakurai-Sugiura CBS library.
+//
+// Vector storage on the device is "pair-interleaved": for every BiCG run
+// (quadrature node j, right-hand side l) the primal vector and its dual are
+// stored side by side per grid point, Pair{primal, dual}, so one thread
+// handles both recurrences of a run and the dual's scalars (conj(alpha),
+// conj(beta)) come for free.  Run r occupies points [r*N, (r+1)*N).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "cbs.h"
+
+namespace cbs {
+
+// ---------------------------------------------------------------- complex
+template <typename R> struct cvec;
+template <> struct cvec<double> { using T = double2; };
+template <> struct cvec<float> { using T = float2; };
+template <typename R> using cplx = typename cvec<R>::T;
+
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> mkc(R re, R im) { cplx<R> c; c.x = re; c.y = im; return c; }
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cadd(cplx<R> a, cplx<R> b) { return mkc<R>(a.x + b.x, a.y + b.y); }
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> csub(cplx<R> a, cplx<R> b) { return mkc<R>(a.x - b.x, a.y - b.y); }
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+  return mkc<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cmulc(cplx<R> a, cplx<R> b) {
+  return mkc<R>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cconj(cplx<R> a) { return mkc<R>(a.x, -a.y); }
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cscale(cplx<R> a, R s) { return mkc<R>(a.x * s, a.y * s); }
+// a + s * b (s real)
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cfma_r(cplx<R> a, R s, cplx<R> b) {
+  return mkc<R>(a.x + s * b.x, a.y + s * b.y);
+}
+// a + c * b (c complex)
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cfma(cplx<R> a, cplx<R> c, cplx<R> b) {
+  return mkc<R>(a.x + c.x * b.x - c.y * b.y, a.y + c.x * b.y + c.y * b.x);
+}
+template <typename R>
+__host__ __device__ __forceinline__ R cabs2(cplx<R> a) { return a.x * a.x + a.y * a.y; }
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cdiv(cplx<R> a, cplx<R> b) {
+  R d = b.x * b.x + b.y * b.y;
+  return mkc<R>((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+template <typename Ro, typename Ri>
+__host__ __device__ __forceinline__ cplx<Ro> ccast(cplx<Ri> a) { return mkc<Ro>((Ro)a.x, (Ro)a.y); }
+
+template <typename R>
+struct alignas(2 * sizeof(cplx<R>)) Pair {
+  cplx<R> a;  // primal
+  cplx<R> b;  // dual
+};
+
+// ------------------------------------------------------------- run state
+enum RunStatus : int32_t {
+  RUN_ACTIVE = 0,
+  RUN_RU = 1,        // marked for a reliable update (FP64 residual replacement) this iteration
+  RUN_DONE = 2,      // converged (true FP64 residual below tol)
+  RUN_NOCONV = 3,    // stopped at max_iter
+  RUN_BREAKDOWN = 4, // rho or sigma vanished
+  RUN_HALTED = 5     // stopped by the half-of-the-nodes rule
+};
+
+// Coefficient triple of one vector: y = c0 (H0-E) x + cp H+ x + cm H- x.
+// Per run: [primal c0, cp, cm, dual c0, cp, cm] as complex doubles.
+struct RunCoef {
+  double2 c[6];
+};
+
+// ------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+const char* get_error();
+
+#define CBS_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::cbs::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call, hipGetErrorString(e_)); \
+      return CBS_EHIP;                                                                 \
+    }                                                                                  \
+  } while (0)
+
+#define CBS_TRY(expr)               \
+  do {                              \
+    int32_t rc_ = (expr);           \
+    if (rc_ != CBS_OK) return rc_;  \
+  } while (0)
+
+// ------------------------------------------------------------- buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Grow-only device workspace keyed by name.
+struct Workspace {
+  std::map<std::string, DevBuf> bufs;
+  int32_t get(const char* name, size_t bytes, void** out);
+  void release();
+};
+
+template <typename T>
+int32_t ws_get(Workspace& ws, const char* name, size_t count, T** out) {
+  void* p = nullptr;
+  int32_t rc = ws.get(name, count * sizeof(T) + 256, &p);
+  *out = static_cast<T*>(p);
+  return rc;
+}
+
+// ------------------------------------------------------------- system
+struct Projector {
+  int32_t n_atoms = 0;
+  int64_t nnz = 0;
+  // atom-major, entries of each atom ordered by shift w: segment s (w = s-1)
+  // of atom a spans [seg[4a+s], seg[4a+s+1]).
+  int32_t* seg = nullptr;        // [4*n_atoms]
+  int32_t* ball_idx = nullptr;   // [nnz] cell point
+  double* ball_u64 = nullptr;    // [nnz*4] (padded to 4 projectors)
+  float* ball_u32 = nullptr;
+  double* coeff64 = nullptr;     // [n_atoms*4]
+  float* coeff32 = nullptr;
+  // point-major index for the ket: entries of point n are [pt_off[n], pt_off[n+1])
+  int32_t* pt_off = nullptr;     // [N+1]
+  int32_t* pt_key = nullptr;     // [nnz] atom*4 + (w+1)
+  double* pt_u64 = nullptr;      // [nnz*4]
+  float* pt_u32 = nullptr;
+  int32_t max_atom_entries = 0;
+};
+
+struct LastSolve {
+  int32_t n = 0;
+  double E = 0;
+  std::vector<double2> lambda;
+  double2* vecs = nullptr;   // device [n][N], owned
+  size_t cap = 0;
+};
+
+}  // namespace cbs
+
+struct cbs_system {
+  int32_t device = 0;
+  int32_t nx = 0, ny = 0, nz = 0, p = 0;
+  double h = 0;
+  int64_t N = 0;
+  double fd[5] = {0, 0, 0, 0, 0};   // c_0 .. c_p of the central second derivative
+  double* vloc64 = nullptr;
+  float* vloc32 = nullptr;
+  cbs::Projector proj;
+  cbs::Workspace ws;
+  cbs::LastSolve last;
+  int32_t tile_y[2] = {0, 0};       // stencil tile rows per precision (0 = double, 1 = float)
+};
+
+namespace cbs {
+
+// ---------------------------------------------------------------- host API of the kernels
+// Launch helpers (all asynchronous on `stream`).
+
+// Local operator (stencil) of every run's pair: see stencil.hip.
+struct StencilLaunch {
+  int32_t nruns;
+  const void* rin;          // BiCG: r; apply: x
+  const void* pold;         // BiCG: previous search direction
+  void* pnew;               // BiCG: new search direction
+  void* q;                  // output: local part of P(z) p
+  void* x;                  // BiCG: x += xcoef * pold
+  const RunCoef* coef;      // [nruns]
+  const double2* beta;      // BiCG [nruns]
+  const double2* xcoef;     // BiCG [nruns]
+  const int32_t* status;    // BiCG [nruns] (NULL: all active)
+  double2* sig_part;        // BiCG [nruns*ntiles]
+  double E;
+};
+template <typename R>
+int32_t launch_stencil(const cbs_system* s, bool bicg, const StencilLaunch& a, int32_t tile_y,
+                       hipStream_t st);
+int32_t stencil_tiles(const cbs_system* s, int32_t tile_y);
+int32_t default_tile_y(const cbs_system* s, int32_t bytes_per_pair);
+
+// Nonlocal part: bra (coefficients of every atom) then ket tables.
+template <typename R>
+int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunCoef* coef,
+                   const int32_t* status, int32_t need_status, void* kt, double2* signl,
+                   hipStream_t st);
+
+// Fused pointwise kernels.
+template <typename R>
+int32_t launch_update(const cbs_system* s, int32_t nruns, void* r, const void* q, const void* kt,
+                      const double2* alpha, const int32_t* status, double* part,
+                      int32_t nchunks, hipStream_t st);
+template <typename R>
+int32_t launch_ket_add(const cbs_system* s, int32_t nruns, void* q, const void* kt, hipStream_t st);
+
+int32_t update_chunks(const cbs_system* s);
+
+// Utility conversions between vector-major [v][N] and pair layout.
+template <typename R>
+int32_t launch_to_pairs(int64_t N, int32_t nvec, const void* x, void* pairs, hipStream_t st);
+template <typename R>
+int32_t launch_from_pairs(int64_t N, int32_t nvec, const void* pairs, void* y, hipStream_t st);
+
+// Parts-form apply on complex128 vectors (used by the solver's Rayleigh-Ritz step).
+int32_t apply_parts_dev(cbs_system* s, double E, int32_t n_vec, const double2* c0,
+                        const double2* cp, const double2* cm, const double2* x, double2* y,
+                        hipStream_t st);
+
+}  // namespace cbs

@@ -1,0 +1,368 @@
+// Separable nonlocal projectors (paper Sec. 4: norm-conserving pseudopotentials) and the
+// pointwise kernels that consume them.
+//
+// With the ball values of atom a split by cell shift w (u_{a,i,w}), the nonlocal part
+// of c0 (H0-E) + cp H+ + cm H- is
+//     sum_{a,i} h_ai sum_{w,w'} coef(w'-w) u_{a,i,w} u_{a,i,w'}^T,
+// coef(0) = c0, coef(1) = cp, coef(-1) = cm (P(z): 1, z, 1/z).  It is applied in two
+// passes per run:
+//   bra:  G[a][w'][i] = u_{a,i,w'}^T v            (one workgroup per atom and run)
+//         K[a][w][i]  = h_ai sum_w' coef(w'-w) G[a][w'][i]
+//   ket:  y(n) += sum_{entries e at point n} sum_i u_{e,i} K[a_e][w_e][i]
+// The ket runs inside the pointwise kernels (BiCG residual update, apply), reading a
+// point-major copy of the tables so no two threads ever add into the same point.
+// For BiCG the bra also yields the nonlocal part of sigma = pt^H P p:
+//   sum_{a,i} h_ai conj(ct_ai) c_ai,  c = G_0 + z G_1 + z^-1 G_-1 (dual: 1/conj z).
+#include <algorithm>
+#include <type_traits>
+
+#include "cbs_internal.hpp"
+
+namespace cbs {
+
+template <typename R> struct vec4;
+template <> struct vec4<double> { using T = double4; };
+template <> struct vec4<float> { using T = float4; };
+
+__device__ __forceinline__ int xcd_remap(int bid, int nb) { return (bid & 7) * (nb >> 3) + (bid >> 3); }
+
+template <typename R>
+__device__ __forceinline__ R wsum(R v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------------- bra
+template <typename R>
+struct BraArgs {
+  int32_t n_atoms, nlogical, need_status;
+  int64_t N;
+  const int32_t* seg;
+  const int32_t* idx;
+  const R* u;          // [nnz][4]
+  const R* coeff;      // [n_atoms][4]
+  const Pair<R>* v;
+  const RunCoef* coef;
+  const int32_t* status;
+  Pair<R>* kt;         // [run][atom][3][4]
+  double2* signl;      // [run][atom] or NULL
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_bra(BraArgs<R> a) {
+  __shared__ R red[4][16];
+  __shared__ cplx<R> G[3][4][2];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (lb >= a.nlogical) return;
+  const int run = lb / a.n_atoms;
+  const int atom = lb - run * a.n_atoms;
+  if (a.status != nullptr && a.status[run] != a.need_status) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t base = (int64_t)run * a.N;
+  for (int sgi = 0; sgi < 3; ++sgi) {
+    const int lo = a.seg[4 * atom + sgi], hi = a.seg[4 * atom + sgi + 1];
+    R acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0;
+    for (int e = lo + tid; e < hi; e += 256) {
+      const typename vec4<R>::T uu = reinterpret_cast<const typename vec4<R>::T*>(a.u)[e];
+      const Pair<R> v = a.v[base + a.idx[e]];
+      const R us[4] = {uu.x, uu.y, uu.z, uu.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acc[4 * i + 0] += us[i] * v.a.x;
+        acc[4 * i + 1] += us[i] * v.a.y;
+        acc[4 * i + 2] += us[i] * v.b.x;
+        acc[4 * i + 3] += us[i] * v.b.y;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = wsum<R>(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) red[wv][k] = acc[k];
+    }
+    __syncthreads();
+    if (tid < 16) {
+      const R t = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+      const int i = tid >> 2, part = tid & 3;
+      R* g = reinterpret_cast<R*>(&G[sgi][i][part >> 1]);
+      g[part & 1] = t;
+    }
+    __syncthreads();
+  }
+  const RunCoef cf = a.coef[run];
+  if (tid < 24) {
+    // tid -> (w shift s of the ket entry, projector i, half)
+    const int half = tid & 1, i = (tid >> 1) & 3, sw = tid >> 3;
+    const cplx<R> c0 = ccast<R, double>(cf.c[3 * half + 0]);
+    const cplx<R> cp = ccast<R, double>(cf.c[3 * half + 1]);
+    const cplx<R> cm = ccast<R, double>(cf.c[3 * half + 2]);
+    cplx<R> k = mkc<R>(0, 0);
+#pragma unroll
+    for (int s2 = 0; s2 < 3; ++s2) {
+      const int d = s2 - sw;   // w' - w
+      const cplx<R> cc = (d == 0) ? c0 : (d == 1) ? cp : (d == -1) ? cm : mkc<R>(0, 0);
+      k = cfma<R>(k, cc, G[s2][i][half]);
+    }
+    k = cscale<R>(k, a.coeff[4 * atom + i]);
+    cplx<R>* dst = reinterpret_cast<cplx<R>*>(&a.kt[((int64_t)run * a.n_atoms + atom) * 12 + sw * 4 + i]);
+    dst[half] = k;
+  }
+  if (a.signl != nullptr && tid == 32) {
+    double2 sg = make_double2(0.0, 0.0);
+    const cplx<R> zpa = ccast<R, double>(cf.c[1]), zma = ccast<R, double>(cf.c[2]);
+    const cplx<R> zpb = ccast<R, double>(cf.c[4]), zmb = ccast<R, double>(cf.c[5]);
+    for (int i = 0; i < 4; ++i) {
+      cplx<R> ca = cadd<R>(G[1][i][0], cadd<R>(cmul<R>(zpa, G[2][i][0]), cmul<R>(zma, G[0][i][0])));
+      cplx<R> cb = cadd<R>(G[1][i][1], cadd<R>(cmul<R>(zpb, G[2][i][1]), cmul<R>(zmb, G[0][i][1])));
+      const cplx<R> t = cscale<R>(cmulc<R>(cb, ca), a.coeff[4 * atom + i]);
+      sg.x += (double)t.x;
+      sg.y += (double)t.y;
+    }
+    a.signl[(int64_t)run * a.n_atoms + atom] = sg;
+  }
+}
+
+template <typename R>
+int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunCoef* coef,
+                   const int32_t* status, int32_t need_status, void* kt, double2* signl,
+                   hipStream_t st) {
+  const Projector& pr = s->proj;
+  if (pr.n_atoms == 0 || nruns <= 0) return CBS_OK;
+  BraArgs<R> a;
+  a.n_atoms = pr.n_atoms;
+  a.nlogical = nruns * pr.n_atoms;
+  a.need_status = need_status;
+  a.N = s->N;
+  a.seg = pr.seg;
+  a.idx = pr.ball_idx;
+  a.u = std::is_same<R, double>::value ? (const R*)pr.ball_u64 : (const R*)pr.ball_u32;
+  a.coeff = std::is_same<R, double>::value ? (const R*)pr.coeff64 : (const R*)pr.coeff32;
+  a.v = (const Pair<R>*)v;
+  a.coef = coef;
+  a.status = status;
+  a.kt = (Pair<R>*)kt;
+  a.signl = signl;
+  const int grid = (a.nlogical + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_bra<R>, dim3(grid), dim3(256), 0, st, a);
+  CBS_HIP(hipGetLastError());
+  return CBS_OK;
+}
+
+// ------------------------------------------------------------------------- ket
+template <typename R>
+__device__ __forceinline__ Pair<R> ket_at(int64_t n, int64_t ktbase, const int32_t* pt_off,
+                                          const int32_t* pt_key, const R* pt_u, const Pair<R>* kt) {
+  Pair<R> q;
+  q.a = mkc<R>(0, 0);
+  q.b = q.a;
+  const int lo = pt_off[n], hi = pt_off[n + 1];
+  for (int e = lo; e < hi; ++e) {
+    const int key = pt_key[e];
+    const typename vec4<R>::T uu = reinterpret_cast<const typename vec4<R>::T*>(pt_u)[e];
+    const Pair<R>* k = kt + ktbase + (int64_t)(key >> 2) * 12 + (key & 3) * 4;
+    const R us[4] = {uu.x, uu.y, uu.z, uu.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const Pair<R> kk = k[i];
+      q.a = cfma_r<R>(q.a, us[i], kk.a);
+      q.b = cfma_r<R>(q.b, us[i], kk.b);
+    }
+  }
+  return q;
+}
+
+// --------------------------------------------------------------- BiCG residual update
+// r -= alpha q, rt -= conj(alpha) qt with q = local part + ket; partial sums of
+// rho = rt^H r, ||r||^2, ||rt||^2 per (run, chunk).
+template <typename R>
+struct UpdArgs {
+  int32_t nchunks, nlogical, n_atoms;
+  int64_t N, chunk;
+  Pair<R>* r;
+  const Pair<R>* q;
+  const Pair<R>* kt;
+  const int32_t* pt_off;
+  const int32_t* pt_key;
+  const R* pt_u;
+  const double2* alpha;
+  const int32_t* status;
+  double* part;   // [run][chunk][4]
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
+  __shared__ double red[4][4];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (lb >= a.nlogical) return;
+  const int run = lb / a.nchunks;
+  const int ch = lb - run * a.nchunks;
+  if (a.status[run] != RUN_ACTIVE) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double2 al = a.alpha[run];
+  const cplx<R> aa = mkc<R>((R)al.x, (R)al.y), ab = cconj<R>(aa);
+  const int64_t base = (int64_t)run * a.N;
+  const int64_t ktbase = (int64_t)run * a.n_atoms * 12;
+  const int64_t lo = ch * a.chunk;
+  const int64_t hi = (lo + a.chunk < a.N) ? lo + a.chunk : a.N;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int64_t n = lo + tid; n < hi; n += 256) {
+    Pair<R> q = a.q[base + n];
+    if (a.kt != nullptr) {
+      const Pair<R> k = ket_at<R>(n, ktbase, a.pt_off, a.pt_key, a.pt_u, a.kt);
+      q.a = cadd<R>(q.a, k.a);
+      q.b = cadd<R>(q.b, k.b);
+    }
+    Pair<R> r = a.r[base + n];
+    r.a = csub<R>(r.a, cmul<R>(aa, q.a));
+    r.b = csub<R>(r.b, cmul<R>(ab, q.b));
+    a.r[base + n] = r;
+    const cplx<R> rho = cmulc<R>(r.b, r.a);
+    s0 += (double)rho.x;
+    s1 += (double)rho.y;
+    s2 += (double)cabs2<R>(r.a);
+    s3 += (double)cabs2<R>(r.b);
+  }
+  s0 = wsum<double>(s0);
+  s1 = wsum<double>(s1);
+  s2 = wsum<double>(s2);
+  s3 = wsum<double>(s3);
+  if (lane == 0) {
+    red[wv][0] = s0;
+    red[wv][1] = s1;
+    red[wv][2] = s2;
+    red[wv][3] = s3;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    a.part[((int64_t)run * a.nchunks + ch) * 4 + tid] =
+        red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  }
+}
+
+int32_t update_chunks(const cbs_system* s) {
+  const int64_t per = 256 * 8;
+  return (int32_t)((s->N + per - 1) / per);
+}
+
+template <typename R>
+int32_t launch_update(const cbs_system* s, int32_t nruns, void* r, const void* q, const void* kt,
+                      const double2* alpha, const int32_t* status, double* part, int32_t nchunks,
+                      hipStream_t st) {
+  if (nruns <= 0) return CBS_OK;
+  UpdArgs<R> a;
+  a.nchunks = nchunks;
+  a.nlogical = nruns * nchunks;
+  a.n_atoms = s->proj.n_atoms;
+  a.N = s->N;
+  a.chunk = (s->N + nchunks - 1) / nchunks;
+  a.r = (Pair<R>*)r;
+  a.q = (const Pair<R>*)q;
+  a.kt = (s->proj.n_atoms > 0) ? (const Pair<R>*)kt : nullptr;
+  a.pt_off = s->proj.pt_off;
+  a.pt_key = s->proj.pt_key;
+  a.pt_u = std::is_same<R, double>::value ? (const R*)s->proj.pt_u64 : (const R*)s->proj.pt_u32;
+  a.alpha = alpha;
+  a.status = status;
+  a.part = part;
+  const int grid = (a.nlogical + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_update<R>, dim3(grid), dim3(256), 0, st, a);
+  CBS_HIP(hipGetLastError());
+  return CBS_OK;
+}
+
+// ------------------------------------------------------------------ apply: q += ket
+template <typename R>
+__global__ void __launch_bounds__(256) k_ket_add(int64_t N, int32_t nruns, int32_t n_atoms, Pair<R>* q,
+                                                 const Pair<R>* kt, const int32_t* pt_off,
+                                                 const int32_t* pt_key, const R* pt_u) {
+  const int64_t total = N * nruns;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t run = g / N, n = g - run * N;
+    const Pair<R> k = ket_at<R>(n, run * n_atoms * 12, pt_off, pt_key, pt_u, kt);
+    Pair<R> v = q[g];
+    v.a = cadd<R>(v.a, k.a);
+    v.b = cadd<R>(v.b, k.b);
+    q[g] = v;
+  }
+}
+
+template <typename R>
+int32_t launch_ket_add(const cbs_system* s, int32_t nruns, void* q, const void* kt, hipStream_t st) {
+  if (s->proj.n_atoms == 0 || nruns <= 0) return CBS_OK;
+  const int64_t total = s->N * nruns;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_ket_add<R>, dim3(grid), dim3(256), 0, st, s->N, nruns, s->proj.n_atoms,
+                     (Pair<R>*)q, (const Pair<R>*)kt, s->proj.pt_off, s->proj.pt_key,
+                     std::is_same<R, double>::value ? (const R*)s->proj.pt_u64 : (const R*)s->proj.pt_u32);
+  CBS_HIP(hipGetLastError());
+  return CBS_OK;
+}
+
+// ------------------------------------------------------------------ layout conversions
+template <typename R>
+__global__ void k_to_pairs(int64_t N, int32_t nvec, const cplx<R>* x, Pair<R>* p) {
+  const int64_t npair = (nvec + 1) / 2;
+  const int64_t total = npair * N;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = g / N, n = g - k * N;
+    Pair<R> v;
+    v.a = x[(2 * k) * N + n];
+    v.b = (2 * k + 1 < nvec) ? x[(2 * k + 1) * N + n] : mkc<R>(0, 0);
+    p[g] = v;
+  }
+}
+
+template <typename R>
+__global__ void k_from_pairs(int64_t N, int32_t nvec, const Pair<R>* p, cplx<R>* y) {
+  const int64_t npair = (nvec + 1) / 2;
+  const int64_t total = npair * N;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = g / N, n = g - k * N;
+    const Pair<R> v = p[g];
+    y[(2 * k) * N + n] = v.a;
+    if (2 * k + 1 < nvec) y[(2 * k + 1) * N + n] = v.b;
+  }
+}
+
+template <typename R>
+int32_t launch_to_pairs(int64_t N, int32_t nvec, const void* x, void* pairs, hipStream_t st) {
+  const int64_t total = (int64_t)((nvec + 1) / 2) * N;
+  if (total == 0) return CBS_OK;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_to_pairs<R>, dim3(grid), dim3(256), 0, st, N, nvec, (const cplx<R>*)x,
+                     (Pair<R>*)pairs);
+  CBS_HIP(hipGetLastError());
+  return CBS_OK;
+}
+
+template <typename R>
+int32_t launch_from_pairs(int64_t N, int32_t nvec, const void* pairs, void* y, hipStream_t st) {
+  const int64_t total = (int64_t)((nvec + 1) / 2) * N;
+  if (total == 0) return CBS_OK;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_from_pairs<R>, dim3(grid), dim3(256), 0, st, N, nvec, (const Pair<R>*)pairs,
+                     (cplx<R>*)y);
+  CBS_HIP(hipGetLastError());
+  return CBS_OK;
+}
+
+#define INST(R)                                                                                   \
+  template int32_t launch_bra<R>(const cbs_system*, int32_t, const void*, const RunCoef*,         \
+                                 const int32_t*, int32_t, void*, double2*, hipStream_t);          \
+  template int32_t launch_update<R>(const cbs_system*, int32_t, void*, const void*, const void*,  \
+                                    const double2*, const int32_t*, double*, int32_t,             \
+                                    hipStream_t);                                                 \
+  template int32_t launch_ket_add<R>(const cbs_system*, int32_t, void*, const void*, hipStream_t); \
+  template int32_t launch_to_pairs<R>(int64_t, int32_t, const void*, void*, hipStream_t);         \
+  template int32_t launch_from_pairs<R>(int64_t, int32_t, const void*, void*, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace cbs

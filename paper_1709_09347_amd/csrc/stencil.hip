@@ -1,0 +1,315 @@
+// Local part of the operator P(z) = (H0 - E) + z H+ + z^{-1} H- (paper Sec. 2, Eq. 4):
+// the -1/2 finite-difference Laplacian, the local potential and the Bloch phases of
+// the z wrap, applied to every run (primal and dual vector side by side).
+//
+// Kernel design (gfx950):
+//  * one workgroup = one run x one tile of TY full x-rows (x periodic inside the tile),
+//    marching over all z planes; the y halo (p rows each side) comes through L2;
+//  * the plane being processed is staged in LDS (double-buffered, one barrier per plane)
+//    for the x and y neighbours; the z direction never touches LDS: every thread keeps
+//    a queue of 2p+1 partial outputs in registers, plane m adds c_{m-o} * v_m to the
+//    outputs o = m-p..m+p, and output m-p is complete after plane m;
+//  * planes below 0 and above nz-1 are the neighbouring cells: they are loaded for the
+//    owning column only and carry the coefficients cm (= 1/z) and cp (= z);
+//  * BiCG mode fuses p_new = r + beta p_old (dual: conj(beta)), x += xcoef * p_old,
+//    the write of p_new and the local part of sigma = pt^H q;
+//  * blocks are renumbered so that consecutive tiles of a run land on one XCD, where
+//    they share the halo rows in that XCD's L2.
+#include <type_traits>
+
+#include "cbs_internal.hpp"
+
+namespace cbs {
+
+template <typename R>
+struct StArgs {
+  int32_t nx, ny, nz, ty, ntiles, nlogical, nbuf;
+  int64_t N;
+  R kin;      // -1/(2 h^2)
+  R c[5];     // c_0..c_p
+  R E;
+  const R* vloc;
+  const Pair<R>* rin;
+  const Pair<R>* pold;
+  Pair<R>* pnew;
+  Pair<R>* q;
+  Pair<R>* x;
+  const RunCoef* coef;
+  const double2* beta;
+  const double2* xcoef;
+  const int32_t* status;
+  double2* sig_part;
+};
+
+__device__ __forceinline__ double2 wave_sum(double2 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+template <typename R, int P, bool BICG>
+__global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double2 red[8];
+  Pair<R>* lds = reinterpret_cast<Pair<R>*>(smem_raw);
+
+  const int nb = gridDim.x;
+  const int bid = blockIdx.x;
+  const int lb = (bid & 7) * (nb >> 3) + (bid >> 3);
+  if (lb >= a.nlogical) return;
+  const int run = lb / a.ntiles;
+  const int tile = lb - run * a.ntiles;
+  if (BICG && a.status != nullptr && a.status[run] != RUN_ACTIVE) return;
+
+  const int nx = a.nx, ny = a.ny, nz = a.nz, TY = a.ty;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int tx = tid % nx;
+  const int ty = tid / nx;
+  const int y = tile * TY + ty;
+  const bool own = (y < ny);
+  const int64_t plane = (int64_t)nx * ny;
+  const int64_t base = (int64_t)run * a.N;
+  const int rows = TY + 2 * P;
+  const int region = rows * nx;
+  const int y0 = tile * TY - P;
+
+  const RunCoef cf = a.coef[run];
+  const cplx<R> c0a = ccast<R, double>(cf.c[0]), cpa = ccast<R, double>(cf.c[1]),
+                cma = ccast<R, double>(cf.c[2]);
+  const cplx<R> c0b = ccast<R, double>(cf.c[3]), cpb = ccast<R, double>(cf.c[4]),
+                cmb = ccast<R, double>(cf.c[5]);
+  cplx<R> ba = mkc<R>(0, 0), bb = ba, xa = ba, xb = ba;
+  bool do_x = false;
+  if (BICG) {
+    const double2 bt = a.beta[run];
+    ba = mkc<R>((R)bt.x, (R)bt.y);
+    bb = cconj<R>(ba);
+    const double2 xc = a.xcoef[run];
+    xa = mkc<R>((R)xc.x, (R)xc.y);
+    xb = cconj<R>(xa);
+    do_x = (xc.x != 0.0 || xc.y != 0.0);
+  }
+  R zc[2 * P + 1];
+#pragma unroll
+  for (int d = 0; d <= 2 * P; ++d) zc[d] = a.kin * a.c[d > P ? d - P : P - d];
+
+  Pair<R> acc[2 * P + 1];
+#pragma unroll
+  for (int d = 0; d <= 2 * P; ++d) {
+    acc[d].a = mkc<R>(0, 0);
+    acc[d].b = mkc<R>(0, 0);
+  }
+  cplx<R> pdq[P + 1];
+#pragma unroll
+  for (int d = 0; d <= P; ++d) pdq[d] = mkc<R>(0, 0);
+  double2 sig = make_double2(0.0, 0.0);
+
+  for (int m = -P; m < nz + P; ++m) {
+    const bool real = (m >= 0) && (m < nz);
+    Pair<R> s;
+    s.a = mkc<R>(0, 0);
+    s.b = s.a;
+    Pair<R> inb = s;
+    if (real) {
+      Pair<R>* buf = lds + ((a.nbuf == 2) ? (m & 1) * region : 0);
+      if (a.nbuf == 1 && m > 0) __syncthreads();   // single buffer: previous plane fully read
+      for (int e = tid; e < region; e += nthr) {
+        const int r = e / nx;
+        const int xx = e - r * nx;
+        const int uy = y0 + r;
+        int gy = uy % ny;
+        if (gy < 0) gy += ny;
+        const int64_t n = base + xx + (int64_t)nx * gy + plane * m;
+        Pair<R> v = a.rin[n];
+        if (BICG) {
+          const Pair<R> po = a.pold[n];
+          v.a = cfma<R>(v.a, ba, po.a);
+          v.b = cfma<R>(v.b, bb, po.b);
+          if (r >= P && r < P + TY && uy < ny) {
+            a.pnew[n] = v;
+            if (do_x) {
+              Pair<R> xv = a.x[n];
+              xv.a = cfma<R>(xv.a, xa, po.a);
+              xv.b = cfma<R>(xv.b, xb, po.b);
+              a.x[n] = xv;
+            }
+          }
+        }
+        buf[e] = v;
+      }
+      __syncthreads();
+      if (own) {
+        const int row = (ty + P) * nx;
+        const Pair<R> v = buf[row + tx];
+        cplx<R> sa = cscale<R>(v.a, (R)2 * a.c[0]);
+        cplx<R> sb = cscale<R>(v.b, (R)2 * a.c[0]);
+#pragma unroll
+        for (int j = 1; j <= P; ++j) {
+          int xl = tx - j;
+          xl += (xl < 0) ? nx : 0;
+          xl += (xl < 0) ? nx : 0;   // nx may be smaller than p
+          xl += (xl < 0) ? nx : 0;
+          xl += (xl < 0) ? nx : 0;
+          int xr = tx + j;
+          xr -= (xr >= nx) ? nx : 0;
+          xr -= (xr >= nx) ? nx : 0;
+          xr -= (xr >= nx) ? nx : 0;
+          xr -= (xr >= nx) ? nx : 0;
+          const Pair<R> l = buf[row + xl];
+          const Pair<R> rr = buf[row + xr];
+          const Pair<R> dn = buf[row - j * nx + tx];
+          const Pair<R> up = buf[row + j * nx + tx];
+          const R cj = a.c[j];
+          sa = cfma_r<R>(sa, cj, cadd<R>(cadd<R>(l.a, rr.a), cadd<R>(dn.a, up.a)));
+          sb = cfma_r<R>(sb, cj, cadd<R>(cadd<R>(l.b, rr.b), cadd<R>(dn.b, up.b)));
+        }
+        const R vd = a.vloc[tx + (int64_t)nx * y + plane * m] - a.E;
+        sa = cfma_r<R>(cscale<R>(sa, a.kin), vd, v.a);
+        sb = cfma_r<R>(cscale<R>(sb, a.kin), vd, v.b);
+        inb.a = cmul<R>(c0a, sa);
+        inb.b = cmul<R>(c0b, sb);
+        s.a = cmul<R>(c0a, v.a);
+        s.b = cmul<R>(c0b, v.b);
+        pdq[P] = v.b;
+      }
+    } else if (own) {
+      const int iz = (m < 0) ? m + nz : m - nz;
+      const int64_t n = base + tx + (int64_t)nx * y + plane * iz;
+      Pair<R> v = a.rin[n];
+      if (BICG) {
+        const Pair<R> po = a.pold[n];
+        v.a = cfma<R>(v.a, ba, po.a);
+        v.b = cfma<R>(v.b, bb, po.b);
+      }
+      if (m < 0) {
+        s.a = cmul<R>(cma, v.a);
+        s.b = cmul<R>(cmb, v.b);
+      } else {
+        s.a = cmul<R>(cpa, v.a);
+        s.b = cmul<R>(cpb, v.b);
+      }
+    }
+    if (own) {
+#pragma unroll
+      for (int d = 0; d <= 2 * P; ++d) {
+        acc[d].a = cfma_r<R>(acc[d].a, zc[d], s.a);
+        acc[d].b = cfma_r<R>(acc[d].b, zc[d], s.b);
+      }
+      if (real) {
+        acc[P].a = cadd<R>(acc[P].a, inb.a);
+        acc[P].b = cadd<R>(acc[P].b, inb.b);
+      }
+      const int o = m - P;
+      if (o >= 0) {
+        a.q[base + tx + (int64_t)nx * y + plane * o] = acc[0];
+        if (BICG) {
+          const cplx<R> t = cmulc<R>(pdq[0], acc[0].a);
+          sig.x += (double)t.x;
+          sig.y += (double)t.y;
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < 2 * P; ++d) acc[d] = acc[d + 1];
+      acc[2 * P].a = mkc<R>(0, 0);
+      acc[2 * P].b = mkc<R>(0, 0);
+#pragma unroll
+      for (int d = 0; d < P; ++d) pdq[d] = pdq[d + 1];
+    }
+  }
+
+  if (BICG) {
+    sig = wave_sum(sig);
+    const int lane = tid & 63, wv = tid >> 6;
+    if (lane == 0) red[wv] = sig;
+    __syncthreads();
+    if (tid == 0) {
+      double2 t = make_double2(0.0, 0.0);
+      for (int w = 0; w < (nthr + 63) / 64; ++w) {
+        t.x += red[w].x;
+        t.y += red[w].y;
+      }
+      a.sig_part[(int64_t)run * a.ntiles + tile] = t;
+    }
+  }
+}
+
+int32_t stencil_tiles(const cbs_system* s, int32_t tile_y) { return (s->ny + tile_y - 1) / tile_y; }
+
+int32_t default_tile_y(const cbs_system* s, int32_t bytes_per_pair) {
+  int best = 1;
+  double best_cost = 1e30;
+  for (int ty = 1; ty <= 16 && ty <= s->ny; ++ty) {
+    if (s->nx * ty > 512) break;
+    const size_t lds = (size_t)(ty + 2 * s->p) * s->nx * bytes_per_pair;   // single buffer
+    if (lds > 64 * 1024) break;
+    const int ntile = (s->ny + ty - 1) / ty;
+    double cost = (double)(ty + 2 * s->p) / ty * ((double)ntile * ty / s->ny);
+    if (s->nx * ty < 128) cost *= 1.25;   // too few waves per workgroup
+    if (cost <= best_cost) {
+      best_cost = cost;
+      best = ty;
+    }
+  }
+  return best;
+}
+
+template <typename R, int P, bool BICG>
+static int32_t launch_p(const cbs_system* s, const StArgs<R>& a, hipStream_t st) {
+  const int nthr = s->nx * a.ty;
+  const size_t smem = (size_t)a.nbuf * (a.ty + 2 * P) * s->nx * sizeof(Pair<R>);
+  if (smem > 64 * 1024) {
+    set_error("stencil tile of %d rows x %d needs %zu bytes of LDS", a.ty, s->nx, smem);
+    return CBS_EINVAL;
+  }
+  const int grid = (a.nlogical + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_stencil<R, P, BICG>), dim3(grid), dim3(nthr), smem, st, a);
+  CBS_HIP(hipGetLastError());
+  return CBS_OK;
+}
+
+template <typename R>
+int32_t launch_stencil(const cbs_system* s, bool bicg, const StencilLaunch& l, int32_t tile_y,
+                       hipStream_t st) {
+  if (l.nruns <= 0) return CBS_OK;
+  StArgs<R> a;
+  a.nx = s->nx;
+  a.ny = s->ny;
+  a.nz = s->nz;
+  a.ty = tile_y;
+  a.ntiles = stencil_tiles(s, tile_y);
+  a.nbuf = ((size_t)2 * (tile_y + 2 * s->p) * s->nx * sizeof(Pair<R>) <= 64 * 1024) ? 2 : 1;
+  a.nlogical = l.nruns * a.ntiles;
+  a.N = s->N;
+  a.kin = (R)(-0.5 / (s->h * s->h));
+  for (int i = 0; i < 5; ++i) a.c[i] = (R)s->fd[i];
+  a.E = (R)l.E;
+  a.vloc = std::is_same<R, double>::value ? (const R*)s->vloc64 : (const R*)s->vloc32;
+  a.rin = (const Pair<R>*)l.rin;
+  a.pold = (const Pair<R>*)l.pold;
+  a.pnew = (Pair<R>*)l.pnew;
+  a.q = (Pair<R>*)l.q;
+  a.x = (Pair<R>*)l.x;
+  a.coef = l.coef;
+  a.beta = l.beta;
+  a.xcoef = l.xcoef;
+  a.status = l.status;
+  a.sig_part = l.sig_part;
+  switch (s->p) {
+    case 1: return bicg ? launch_p<R, 1, true>(s, a, st) : launch_p<R, 1, false>(s, a, st);
+    case 2: return bicg ? launch_p<R, 2, true>(s, a, st) : launch_p<R, 2, false>(s, a, st);
+    case 3: return bicg ? launch_p<R, 3, true>(s, a, st) : launch_p<R, 3, false>(s, a, st);
+    case 4: return bicg ? launch_p<R, 4, true>(s, a, st) : launch_p<R, 4, false>(s, a, st);
+    default: set_error("unsupported finite-difference half-width %d", s->p); return CBS_EINVAL;
+  }
+}
+
+template int32_t launch_stencil<double>(const cbs_system*, bool, const StencilLaunch&, int32_t,
+                                        hipStream_t);
+template int32_t launch_stencil<float>(const cbs_system*, bool, const StencilLaunch&, int32_t,
+                                       hipStream_t);
+
+}  // namespace cbs

@@ -16,3 +16,11 @@ def pytest_configure(config):
 def pytest_collection_modifyitems(config, items):
     # GPU tests go last so that CPU failures show first under -x.
     items.sort(key=lambda it: 1 if it.get_closest_marker("gpu") else 0)
+
+
+@pytest.fixture(scope="session")
+def cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")

@@ -1,0 +1,95 @@
+"""Parity of the operator kernels (stencil + projectors, Eq. 4) with the oracle.
+
+FP64: relative error <= 1e-13 of ||P|| ||x|| per vector (a handful of roundings of
+terms bounded by ||P|| |x|).  FP32: <= 2e-6 of the same scale (float epsilon 6e-8
+times a few dozen terms).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ham, qep
+
+pytestmark = pytest.mark.gpu
+
+
+def _zs(n, seed):
+    rng = np.random.default_rng(seed)
+    mag = np.exp(rng.uniform(np.log(0.4), np.log(2.5), n))
+    mag[0] = 1.0
+    return mag * np.exp(1j * rng.uniform(-np.pi, np.pi, n))
+
+
+def _check(sysw, E, nvec, cuda, seed=0, dtype="c128"):
+    import torch
+    import paper_1709_09347_amd as cbs
+    H = ham.build(sysw)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((nvec, sysw.n)) + 1j * rng.standard_normal((nvec, sysw.n))
+    z = _zs(nvec, seed + 1)
+    s = cbs.System.from_workload(sysw)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    xt = torch.from_numpy(x).to(cuda).to(tdt)
+    y = s.apply(E, z, xt).cpu().numpy().astype(np.complex128)
+    want = np.stack([H.apply(z[v], xt[v].cpu().numpy().astype(np.complex128), E) for v in range(nvec)])
+    scale = np.abs(want).max(axis=1, keepdims=True) + np.abs(x).max(axis=1, keepdims=True) * 50
+    err = np.abs(y - want) / scale
+    tol = 1e-13 if dtype == "c128" else 2e-6
+    assert err.max() <= tol, (err.max(), sysw.name, E, nvec, dtype)
+    return s
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_apply_tiny_projectors(cuda, dtype):
+    _check(W.tiny(with_proj=True, fd_order=8), 0.7, 5, cuda, dtype=dtype)
+
+
+@pytest.mark.parametrize("fd_order", [2, 4, 6, 8])
+def test_apply_fd_orders_cfg1_grid(cuda, fd_order):
+    s = W.config(1).systems[0]
+    s = W.System(s.nx, s.ny, s.nz, s.h, fd_order, s.v_loc, s.centres, s.amps, None, "cfg1")
+    _check(s, 0.3, 4, cuda)
+
+
+def test_apply_ragged_tiles_and_small_x(cuda):
+    # nx smaller than the stencil half-width (x wraps several times), ny prime
+    s = W.make_system(3, 7, 9, 0.45, 8, 2, 77, 78, with_proj=True, r_c=1.2, name="odd")
+    _check(s, -0.2, 3, cuda)
+    s = W.make_system(13, 11, 4, 0.5, 8, 2, 79, name="nz_eq_p")
+    _check(s, 0.1, 2, cuda)
+
+
+def test_apply_cfg2_full_size(cuda):
+    # the bench workload's grid and projectors, compared in full against the sparse oracle
+    _check(W.config(2).systems[0], 0.2, 4, cuda, seed=3)
+    _check(W.config(2).systems[0], 0.2, 3, cuda, seed=4, dtype="c64")
+
+
+def test_apply_parts_match_blocks(cuda):
+    import torch
+    import paper_1709_09347_amd as cbs
+    sysw = W.tiny(with_proj=True, fd_order=8)
+    h0, hp, hm = ham.build(sysw).blocks_dense()
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((3, sysw.n)) + 1j * rng.standard_normal((3, sysw.n))
+    s = cbs.System.from_workload(sysw)
+    E = 0.4
+    one, zero = np.ones(3), np.zeros(3)
+    xt = torch.from_numpy(x).to(cuda)
+    y0 = s.apply_parts(E, one, zero, zero, xt).cpu().numpy()
+    yp = s.apply_parts(E, zero, one, zero, xt).cpu().numpy()
+    ym = s.apply_parts(E, zero, zero, one, xt).cpu().numpy()
+    np.testing.assert_allclose(y0, (x @ (h0 - E * np.eye(sysw.n)).T), atol=1e-12)
+    np.testing.assert_allclose(yp, x @ hp.T, atol=1e-12)
+    np.testing.assert_allclose(ym, x @ hm.T, atol=1e-12)
+
+
+def test_apply_rejects_bad_input(cuda):
+    import torch
+    import paper_1709_09347_amd as cbs
+    s = cbs.System.from_workload(W.tiny())
+    x = torch.zeros((2, s.n), dtype=torch.complex128, device=cuda)
+    with pytest.raises(cbs.CbsError):
+        s.apply(0.1, [1.0, 0.0], x)
+    with pytest.raises(cbs.CbsError):
+        cbs.System(4, 4, 1, 0.3, 8, np.zeros(16))   # nz < p
