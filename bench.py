@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Time per energy of the Sakurai-Sugiura complex-band-structure solve on one MI355X.
+
+Workload: the 48x48x32 cell (h = 0.3 bohr, 8th-order finite differences) with 96
+pseudo-atoms on a cylinder of radius 6 bohr (Gaussian local potential plus four
+Gaussian-supported projectors each), E = 0.2 Ha, annulus 0.5 < |lambda| < 2,
+N_q = 32 nodes per circle, L = 16 right-hand sides, M = 8 moments, every linear
+solve to a 1e-10 relative residual.  Inputs are seeded and synthetic and resident
+in device memory before the timed region.
+
+One step = one complete solve at one energy (BiCG with duals at all nodes, moments,
+Hankel SVD, Rayleigh-Ritz extraction, residuals).  The mixed-precision path
+(complex64 BiCG with complex128 residual replacement) is the reported value; the
+complex128 path is timed beside it on the same inputs.
+
+The JSON line also carries the roofline of the dominant kernel (the BiCG stencil,
+timed per launch with HIP events on the stream it runs on in a diagnostic solve
+after the timed region) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time per energy to 1e-10 residual (mixed vs FP64 GPU); stencil HBM GB/s"
+# HBM bytes per dispatch of the stencil from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB), scaled by
+# the copy-kernel calibration; None until the counters have been taken for the current kernel.
+STENCIL_TRAFFIC_BYTES = None
+
+
+def cpu_baseline(sysw, E, V, iters_per_run, n_runs, budget_s=12.0):
+    """The oracle's BiCG (scipy.sparse operator) on one run, time-bounded, extrapolated."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ham, ss
+    H = ham.build(sysw)
+    z1, _, _, _ = ss.quadrature(0.5, 32)
+    z = z1[0]
+    v = V[0]
+    done, t_used = 0, 0.0
+    with threadpool_limits(limits=1):
+        while t_used < budget_s:
+            t0 = time.perf_counter()
+            ss.bicg(lambda u: H.apply(z, u, E), lambda u: H.apply(1 / np.conj(z), u, E), v, v,
+                    fixed_iters=10)
+            t_used += time.perf_counter() - t0
+            done += 10
+    per_iter = t_used / done
+    return {
+        "value": per_iter * iters_per_run * n_runs,
+        "unit": "s/energy",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{done} BiCG iterations (primal+dual) of one run on the oracle's scipy.sparse "
+                   f"operator at this workload ({t_used:.1f} s, 1 thread), extrapolated to {n_runs} runs "
+                   f"x {iters_per_run:.0f} iterations (the GPU FP64 solve's mean); moments and "
+                   f"extraction not included"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the path shards by quadrature node and "
+              "right-hand side; multi-GPU runs are not part of it)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1709_09347_amd as cbs
+    import workloads as W
+    from oracle import qep
+
+    dev = torch.device("cuda:0")
+    w = W.config(2)
+    sysw = w.systems[0]
+    E = w.solve.energies[0]
+    L, M = w.solve.n_rhs, w.solve.n_mom
+    Vh = W.make_rhs(sysw.n, L, w.seed_rhs)
+    s = cbs.System.from_workload(sysw)
+    V = torch.from_numpy(Vh).to(dev)
+    torch.cuda.synchronize()
+
+    runs = {}
+    for name, prec in (("fp64", cbs.CBS_FP64), ("mixed", cbs.CBS_MIXED)):
+        prm = cbs.default_params(n_rhs=L, n_mom=M, precision=prec)
+        for _ in range(args.warmup):
+            s.solve(E, V, prm, want_vectors=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lam, _, res, info, rc = s.solve(E, V, prm, want_vectors=False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        runs[name] = dict(t=dt, lam=lam, res=res, info=info, rc=rc)
+        print(f"# {name}: {dt:.3f} s/energy, {len(lam)} eigenvalues, rank {info.rank}, BiCG iters "
+              f"max {info.iters_max} mean {info.iters_mean:.1f}, max solve residual "
+              f"{info.max_solve_resid:.2e}, max eigen residual {info.max_eig_resid:.2e}, rc {rc}",
+              file=sys.stderr, flush=True)
+
+    # dominant kernel: the mixed path's BiCG stencil, timed per launch (diagnostic solve)
+    roof = {}
+    for name, prec in (("mixed", cbs.CBS_MIXED), ("fp64", cbs.CBS_FP64)):
+        prm = cbs.default_params(n_rhs=L, n_mom=M, precision=prec, profile=1)
+        _, _, _, pinfo, _ = s.solve(E, V, prm, want_vectors=False)
+        avg_ms = pinfo.stencil_ms / max(pinfo.stencil_launches, 1)
+        avg_bytes = pinfo.stencil_bytes / max(pinfo.stencil_launches, 1)
+        gbs = avg_bytes / (avg_ms * 1e-3) / 1e9
+        roof[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": STENCIL_TRAFFIC_BYTES,
+                      "kernel": f"k_stencil<{'float' if prec else 'double'},4,true>",
+                      "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": avg_bytes,
+                      "launches": int(pinfo.stencil_launches)}
+        print(f"# stencil ({name}): {avg_ms:.3f} ms/launch, {gbs:.0f} GB/s over "
+              f"{pinfo.stencil_launches} launches", file=sys.stderr, flush=True)
+
+    mixed, fp64 = runs["mixed"], runs["fp64"]
+    dl = qep.match_sets(mixed["lam"], fp64["lam"]) if len(mixed["lam"]) == len(fp64["lam"]) else None
+    out = {
+        "metric": METRIC,
+        "value": round(mixed["t"], 4),
+        "unit": "s/energy",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed["t"] * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+c128",
+        "data": "synthetic",
+        "config": {"workload": "48x48x32 h=0.3 fd8, 96 atoms x 4 projectors, E=0.2 Ha, N_q=32, "
+                               "L=16, M=8, tol 1e-10 (configs[1])",
+                   "global_batch": 32 * L, "seq_len": sysw.n, "parallelism": "none"},
+        "fp64_s_per_energy": round(fp64["t"], 4),
+        "speedup_mixed_vs_fp64": round(fp64["t"] / mixed["t"], 3),
+        "n_eigs": int(len(mixed["lam"])),
+        "lambda_rel_diff_mixed_vs_fp64": dl,
+        "max_eig_resid": float(max(mixed["info"].max_eig_resid, fp64["info"].max_eig_resid)),
+        "bicg_iters_mean": {"fp64": fp64["info"].iters_mean, "mixed": mixed["info"].iters_mean},
+        "roofline": roof["mixed"],
+        "roofline_fp64": roof["fp64"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sysw, E, Vh, fp64["info"].iters_mean, 32 * L)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

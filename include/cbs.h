@@ -105,6 +105,7 @@ typedef struct {
   double inner_tol;     /* CBS_MIXED: relative tolerance of each complex64 inner solve */
   int32_t max_refine;   /* CBS_MIXED: cap on FP64 refinement steps */
   int32_t chunk;        /* iterations per captured graph between convergence polls (even) */
+  int32_t profile;      /* 1: no graph; HIP events time every BiCG stencil launch (cbs_info.stencil_*) */
 } cbs_params;
 
 /* Per-solve diagnostics. */
@@ -120,6 +121,12 @@ typedef struct {
   double sigma_ratio;       /* sigma_m / sigma_1 of the last kept singular value */
   double t_solve_ms, t_moments_ms, t_extract_ms;   /* wall time of the three steps */
   int64_t matvecs;          /* operator applications (vectors) in the solves */
+  /* params.profile = 1 only: the BiCG stencil kernel, timed per launch with HIP events on
+   * the stream it runs on; bytes are its algorithmic traffic (per active run: read r,
+   * p_old, x and write p_new, q, x once, plus V_loc once per launch). */
+  int64_t stencil_launches;
+  double stencil_ms;
+  double stencil_bytes;
 } cbs_info;
 
 /* ---- errors ---------------------------------------------------------- */

@@ -55,7 +55,7 @@ class Params(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("extraction", ctypes.c_int32), ("half_stop", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("chunk", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("profile", ctypes.c_int32)]
 
     def __repr__(self):
         return "Params(" + ", ".join(f"{n}={getattr(self, n)}" for n, _ in self._fields_) + ")"
@@ -67,7 +67,9 @@ class Info(ctypes.Structure):
                 ("max_solve_resid", ctypes.c_double), ("max_eig_resid", ctypes.c_double),
                 ("sigma_first", ctypes.c_double), ("sigma_ratio", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_moments_ms", ctypes.c_double),
-                ("t_extract_ms", ctypes.c_double), ("matvecs", ctypes.c_int64)]
+                ("t_extract_ms", ctypes.c_double), ("matvecs", ctypes.c_int64),
+                ("stencil_launches", ctypes.c_int64), ("stencil_ms", ctypes.c_double),
+                ("stencil_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

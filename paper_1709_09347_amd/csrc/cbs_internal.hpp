@@ -84,7 +84,48 @@ enum RunStatus : int32_t {
 // Per run: [primal c0, cp, cm, dual c0, cp, cm] as complex doubles.
 struct RunCoef {
   double2 c[6];
+  double E;        // energy of the run (batched solves mix energies)
+  double pad;
 };
+
+template <typename R> struct vec4;
+template <> struct vec4<double> { using T = double4; };
+template <> struct vec4<float> { using T = float4; };
+
+// Remap a block id so that consecutive logical blocks run on one XCD (the
+// dispatcher hands blocks to the 8 XCDs round-robin); gridDim must be a
+// multiple of 8.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) { return (bid & 7) * (nb >> 3) + (bid >> 3); }
+
+template <typename R>
+__device__ __forceinline__ R wsum(R v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Ket of the nonlocal projectors at point n (see nonlocal.hip).
+template <typename R>
+__device__ __forceinline__ Pair<R> ket_at(int64_t n, int64_t ktbase, const int32_t* pt_off,
+                                          const int32_t* pt_key, const R* pt_u, const Pair<R>* kt) {
+  Pair<R> q;
+  q.a = mkc<R>(0, 0);
+  q.b = q.a;
+  const int lo = pt_off[n], hi = pt_off[n + 1];
+  for (int e = lo; e < hi; ++e) {
+    const int key = pt_key[e];
+    const typename vec4<R>::T uu = reinterpret_cast<const typename vec4<R>::T*>(pt_u)[e];
+    const Pair<R>* k = kt + ktbase + (int64_t)(key >> 2) * 12 + (key & 3) * 4;
+    const R us[4] = {uu.x, uu.y, uu.z, uu.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const Pair<R> kk = k[i];
+      q.a = cfma_r<R>(q.a, us[i], kk.a);
+      q.b = cfma_r<R>(q.b, us[i], kk.b);
+    }
+  }
+  return q;
+}
 
 // ------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
@@ -186,9 +227,9 @@ struct StencilLaunch {
   const RunCoef* coef;      // [nruns]
   const double2* beta;      // BiCG [nruns]
   const double2* xcoef;     // BiCG [nruns]
-  const int32_t* status;    // BiCG [nruns] (NULL: all active)
+  const int32_t* status;    // [nruns] or NULL (no filter)
+  int32_t need_status;      // blocks of runs whose status differs return at once
   double2* sig_part;        // BiCG [nruns*ntiles]
-  double E;
 };
 template <typename R>
 int32_t launch_stencil(const cbs_system* s, bool bicg, const StencilLaunch& a, int32_t tile_y,

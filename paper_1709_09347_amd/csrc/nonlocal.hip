@@ -20,19 +20,6 @@
 
 namespace cbs {
 
-template <typename R> struct vec4;
-template <> struct vec4<double> { using T = double4; };
-template <> struct vec4<float> { using T = float4; };
-
-__device__ __forceinline__ int xcd_remap(int bid, int nb) { return (bid & 7) * (nb >> 3) + (bid >> 3); }
-
-template <typename R>
-__device__ __forceinline__ R wsum(R v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // ------------------------------------------------------------------------- bra
 template <typename R>
 struct BraArgs {
@@ -149,29 +136,6 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
   hipLaunchKernelGGL(k_bra<R>, dim3(grid), dim3(256), 0, st, a);
   CBS_HIP(hipGetLastError());
   return CBS_OK;
-}
-
-// ------------------------------------------------------------------------- ket
-template <typename R>
-__device__ __forceinline__ Pair<R> ket_at(int64_t n, int64_t ktbase, const int32_t* pt_off,
-                                          const int32_t* pt_key, const R* pt_u, const Pair<R>* kt) {
-  Pair<R> q;
-  q.a = mkc<R>(0, 0);
-  q.b = q.a;
-  const int lo = pt_off[n], hi = pt_off[n + 1];
-  for (int e = lo; e < hi; ++e) {
-    const int key = pt_key[e];
-    const typename vec4<R>::T uu = reinterpret_cast<const typename vec4<R>::T*>(pt_u)[e];
-    const Pair<R>* k = kt + ktbase + (int64_t)(key >> 2) * 12 + (key & 3) * 4;
-    const R us[4] = {uu.x, uu.y, uu.z, uu.w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const Pair<R> kk = k[i];
-      q.a = cfma_r<R>(q.a, us[i], kk.a);
-      q.b = cfma_r<R>(q.b, us[i], kk.b);
-    }
-  }
-  return q;
 }
 
 // --------------------------------------------------------------- BiCG residual update

@@ -1,0 +1,530 @@
+// The Sakurai-Sugiura method at one energy (paper Sec. 3.1, Algorithm 1, on the ring
+// contour of Sec. 3.2):
+//   1. BiCG with duals at the outer-circle nodes (bicg.hip): Y_j^(1) primal, Y_j^(2) dual
+//   2. moments S_k = sum_j w1_j z1_j^k Y_j^(1) - sum_j w2_j z2_j^k Y_j^(2), k < 2M, and
+//      mu_k = V^H S_k (block inner products on MFMA)
+//   3. block Hankel T_ij = mu_{i+j}, T<_ij = mu_{i+j+1}; SVD T = U S W^H truncated at
+//      sigma > delta sigma_1; reduced problem U1^H T< W1 S1^-1 phi = tau phi
+//   4. eigenpairs: Hankel (lambda, S W1 S1^-1 phi) or, by default, Rayleigh-Ritz: the
+//      QEP projected onto Q = orth(S W1) and solved densely through its linearisation
+//   5. residuals ||P(lambda) psi|| in complex128, the annulus of Eq. 5, sorting.
+// Everything between the solves and the host copy of lambda runs on the device in FP64.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "bicg.hpp"
+#include "cbs_internal.hpp"
+#include "dense.hpp"
+
+namespace cbs {
+
+using c64 = double2;
+
+// Trapezoid nodes and weights on both circles: theta_j = 2 pi (j - 1/2)/n_q,
+// z1 = e^{i theta}/lambda_min, z2 = lambda_min e^{i theta} = 1/conj(z1), w = z/n_q
+// (the trapezoid rule of (1/2 pi i) \oint dz, dz = i z d theta).
+static void quadrature(double lmin, int n_q, std::vector<c64>& z1, std::vector<c64>& w1, std::vector<c64>& z2,
+                       std::vector<c64>& w2) {
+  z1.resize(n_q);
+  w1.resize(n_q);
+  z2.resize(n_q);
+  w2.resize(n_q);
+  for (int j = 0; j < n_q; ++j) {
+    const double th = 2.0 * M_PI * (j + 0.5) / n_q;
+    const double c = cos(th), s = sin(th);
+    z1[j] = make_double2(c / lmin, s / lmin);
+    z2[j] = make_double2(c * lmin, s * lmin);
+    w1[j] = make_double2(z1[j].x / n_q, z1[j].y / n_q);
+    w2[j] = make_double2(z2[j].x / n_q, z2[j].y / n_q);
+  }
+}
+
+// S[k][l][n] for k in [k0, k0+nk): coefficient tables ca[j][k] = w1 z1^k, cb[j][k] = w2 z2^k.
+constexpr int MOM_CHUNK = 8;
+__global__ void __launch_bounds__(256) k_moments(int64_t N, int32_t L, int32_t n_q, int32_t nk_total, int32_t k0,
+                                                 int32_t nk, const Pair<double>* Y, const c64* ca, const c64* cb,
+                                                 c64* S) {
+  const int64_t total = N * L;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = g / N, n = g - l * N;
+    c64 acc[MOM_CHUNK];
+#pragma unroll
+    for (int k = 0; k < MOM_CHUNK; ++k) acc[k] = make_double2(0, 0);
+    for (int j = 0; j < n_q; ++j) {
+      const Pair<double> y = Y[((int64_t)j * L + l) * N + n];
+#pragma unroll
+      for (int k = 0; k < MOM_CHUNK; ++k) {
+        if (k < nk) {
+          const c64 a = ca[j * nk_total + k0 + k], b = cb[j * nk_total + k0 + k];
+          acc[k] = cadd<double>(acc[k], csub<double>(cmul<double>(a, y.a), cmul<double>(b, y.b)));
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < MOM_CHUNK; ++k)
+      if (k < nk) S[((int64_t)(k0 + k) * L + l) * N + n] = acc[k];
+  }
+}
+
+// Block Hankel matrices from mu (C[a + (k L + b) L] = mu_k[a][b]).
+__global__ void k_hankel(int32_t L, int32_t M, const c64* C, c64* T, c64* Tl) {
+  const int n = L * M;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n * n; t += gridDim.x * blockDim.x) {
+    const int r = t % n, c = t / n;
+    const int i = r / L, a = r % L, j = c / L, b = c % L;
+    T[r + (int64_t)c * n] = C[a + (int64_t)((i + j) * L + b) * L];
+    Tl[r + (int64_t)c * n] = C[a + (int64_t)((i + j + 1) * L + b) * L];
+  }
+}
+
+__global__ void k_gather_cols(int32_t n, int32_t m, const c64* src, int32_t lds, const int32_t* perm, c64* dst,
+                              int32_t ldd) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n * m; t += gridDim.x * blockDim.x) {
+    const int i = t % n, j = t / n;
+    dst[i + (int64_t)j * ldd] = src[i + (int64_t)perm[j] * lds];
+  }
+}
+
+// coef = W1 diag(1/s) phi  (n x m)
+__global__ void k_scale_rows_gemm(int32_t n, int32_t m, const c64* W1, const double* sig, const c64* phi, c64* out) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n * m; t += gridDim.x * blockDim.x) {
+    const int i = t % n, j = t / n;
+    c64 acc = make_double2(0, 0);
+    for (int k = 0; k < m; ++k)
+      acc = cadd<double>(acc, cscale<double>(cmul<double>(W1[i + (int64_t)k * n], phi[k + (int64_t)j * m]), 1.0 / sig[k]));
+    out[i + (int64_t)j * n] = acc;
+  }
+}
+
+// Companion linearisation of A- + lam A0 + lam^2 A+ and its shift: X = (A - s B), RHS = B.
+__global__ void k_linearize(int32_t m, const c64* A0, const c64* Ap, const c64* Am, c64 sft, c64* X, c64* B) {
+  const int n = 2 * m;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n * n; t += gridDim.x * blockDim.x) {
+    const int r = t % n, c = t / n;
+    c64 a = make_double2(0, 0), b = make_double2(0, 0);
+    if (r < m && c < m) {
+      b = make_double2(r == c ? 1.0 : 0.0, 0);
+    } else if (r < m && c >= m) {
+      a = make_double2(r == c - m ? 1.0 : 0.0, 0);
+    } else if (r >= m && c < m) {
+      a = cscale<double>(Am[(r - m) + (int64_t)c * m], -1.0);
+    } else {
+      a = cscale<double>(A0[(r - m) + (int64_t)(c - m) * m], -1.0);
+      b = Ap[(r - m) + (int64_t)(c - m) * m];
+    }
+    X[r + (int64_t)c * n] = csub<double>(a, cmul<double>(sft, b));
+    B[r + (int64_t)c * n] = b;
+  }
+}
+
+// Per-vector 2-norm, index of the largest entry; optionally normalise so that entry is real positive.
+__global__ void __launch_bounds__(256) k_vec_norm(int64_t N, const c64* V, int64_t ldv, double* norms, int32_t fix,
+                                                  c64* out, int64_t ldo) {
+  __shared__ double s2[4], smax[4];
+  __shared__ int64_t sidx[4];
+  __shared__ c64 sph;
+  __shared__ double snorm;
+  const int v = blockIdx.x, tid = threadIdx.x;
+  const c64* x = V + (int64_t)v * ldv;
+  double acc = 0, best = -1;
+  int64_t bi = 0;
+  for (int64_t n = tid; n < N; n += 256) {
+    const double a = cabs2<double>(x[n]);
+    acc += a;
+    if (a > best) {
+      best = a;
+      bi = n;
+    }
+  }
+  acc = wsum<double>(acc);
+  for (int o = 1; o < 64; o <<= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int64_t oi = __shfl_xor(bi, o, 64);
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  if ((tid & 63) == 0) {
+    s2[tid >> 6] = acc;
+    smax[tid >> 6] = best;
+    sidx[tid >> 6] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t = s2[0] + s2[1] + s2[2] + s2[3];
+    double b = smax[0];
+    int64_t ii = sidx[0];
+    for (int w = 1; w < 4; ++w)
+      if (smax[w] > b || (smax[w] == b && sidx[w] < ii)) {
+        b = smax[w];
+        ii = sidx[w];
+      }
+    const double nr = sqrt(t);
+    norms[v] = nr;
+    snorm = nr;
+    const c64 e = x[ii];
+    const double ae = sqrt(cabs2<double>(e));
+    sph = (ae > 0) ? make_double2(e.x / ae, -e.y / ae) : make_double2(1, 0);   // conj phase
+  }
+  __syncthreads();
+  if (fix && snorm > 0) {
+    const c64 f = cscale<double>(sph, 1.0 / snorm);
+    for (int64_t n = tid; n < N; n += 256) out[(int64_t)v * ldo + n] = cmul<double>(f, x[n]);
+  }
+}
+
+static int32_t vec_norms(int64_t N, int32_t nv, const c64* V, int64_t ldv, double* norms, bool fix, c64* out,
+                         int64_t ldo, hipStream_t st) {
+  if (nv <= 0) return CBS_OK;
+  hipLaunchKernelGGL(k_vec_norm, dim3(nv), dim3(256), 0, st, N, V, ldv, norms, (int32_t)fix, out, ldo);
+  CBS_HIP(hipGetLastError());
+  return CBS_OK;
+}
+
+static int32_t launch_grid(int64_t work) { return (int32_t)std::min<int64_t>((work + 255) / 256, 4096); }
+
+struct Extracted {
+  std::vector<c64> lam;      // candidates kept (in the annulus, residual-filtered), sorted
+  std::vector<double> res;
+  c64* vecs = nullptr;       // device, [cnt][N] normalised, in sorted order (workspace)
+  int32_t rank = 0;
+  double sig1 = 0, sig_ratio = 0;
+};
+
+// Steps 2-5 for one system / energy; Y = node solutions (pairs, run = j*L + l).
+int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, const Pair<double>* Y,
+                hipStream_t st, Extracted& out, double* t_mom_ms) {
+  const int L = prm->n_rhs, M = prm->n_mom, nq = prm->n_q, nk = 2 * M, n = L * M;
+  const int64_t N = s->N;
+  Workspace& ws = s->ws;
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<c64> z1, w1, z2, w2;
+  quadrature(prm->lambda_min, nq, z1, w1, z2, w2);
+  std::vector<c64> ca((size_t)nq * nk), cb((size_t)nq * nk);
+  for (int j = 0; j < nq; ++j) {
+    c64 pa = w1[j], pb = w2[j];
+    for (int k = 0; k < nk; ++k) {
+      ca[(size_t)j * nk + k] = pa;
+      cb[(size_t)j * nk + k] = pb;
+      pa = cmul<double>(pa, z1[j]);
+      pb = cmul<double>(pb, z2[j]);
+    }
+  }
+  c64 *dca = nullptr, *dcb = nullptr, *S = nullptr, *C = nullptr;
+  CBS_TRY(ws_get(ws, "mom.ca", ca.size(), &dca));
+  CBS_TRY(ws_get(ws, "mom.cb", cb.size(), &dcb));
+  CBS_TRY(ws_get(ws, "mom.S", (size_t)nk * L * N, &S));
+  CBS_TRY(ws_get(ws, "mom.C", (size_t)L * nk * L, &C));
+  CBS_HIP(hipMemcpyAsync(dca, ca.data(), ca.size() * sizeof(c64), hipMemcpyHostToDevice, st));
+  CBS_HIP(hipMemcpyAsync(dcb, cb.data(), cb.size() * sizeof(c64), hipMemcpyHostToDevice, st));
+  for (int k0 = 0; k0 < nk; k0 += MOM_CHUNK) {
+    hipLaunchKernelGGL(k_moments, dim3(launch_grid(N * L)), dim3(256), 0, st, N, L, nq, nk, k0,
+                       std::min(MOM_CHUNK, nk - k0), Y, (const c64*)dca, (const c64*)dcb, S);
+    CBS_HIP(hipGetLastError());
+  }
+  CBS_TRY(gram(s, N, L, V, N, nk * L, S, N, C, L, st));
+  CBS_HIP(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  if (t_mom_ms) *t_mom_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+
+  // --- Hankel SVD
+  c64 *T = nullptr, *Tl = nullptr, *W = nullptr;
+  double* sig = nullptr;
+  int32_t *perm = nullptr, *info = nullptr;
+  CBS_TRY(ws_get(ws, "hk.T", (size_t)n * n, &T));
+  CBS_TRY(ws_get(ws, "hk.Tl", (size_t)n * n, &Tl));
+  CBS_TRY(ws_get(ws, "hk.W", (size_t)n * n, &W));
+  CBS_TRY(ws_get(ws, "hk.sig", 1024, &sig));
+  CBS_TRY(ws_get(ws, "hk.perm", 512, &perm));
+  CBS_TRY(ws_get(ws, "hk.info", 4, &info));
+  CBS_HIP(hipMemsetAsync(info, 0, 4 * sizeof(int32_t), st));
+  hipLaunchKernelGGL(k_hankel, dim3(launch_grid((int64_t)n * n)), dim3(256), 0, st, L, M, (const c64*)C, T, Tl);
+  CBS_HIP(hipGetLastError());
+  CBS_TRY(svd(n, T, n, W, n, sig, perm, st));
+  std::vector<double> hsig(n);
+  CBS_HIP(hipMemcpyAsync(hsig.data(), sig, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  CBS_HIP(hipStreamSynchronize(st));
+  int m = 0;
+  for (int i = 0; i < n; ++i)
+    if (hsig[i] > prm->delta * hsig[0]) ++m;
+  out.rank = m;
+  out.sig1 = hsig[0];
+  out.sig_ratio = (m > 0 && hsig[0] > 0) ? hsig[m - 1] / hsig[0] : 0.0;
+  out.lam.clear();
+  out.res.clear();
+  if (m == 0 || !(hsig[0] > 0)) return CBS_OK;
+
+  // --- reduced Hankel problem
+  c64 *Up = nullptr, *Wp = nullptr, *TW = nullptr, *Bred = nullptr, *tau = nullptr, *phi = nullptr;
+  CBS_TRY(ws_get(ws, "hk.Up", (size_t)n * m, &Up));
+  CBS_TRY(ws_get(ws, "hk.Wp", (size_t)n * m, &Wp));
+  CBS_TRY(ws_get(ws, "hk.TW", (size_t)n * m, &TW));
+  CBS_TRY(ws_get(ws, "hk.B", (size_t)m * m, &Bred));
+  CBS_TRY(ws_get(ws, "hk.tau", (size_t)2 * n, &tau));
+  CBS_TRY(ws_get(ws, "hk.phi", (size_t)m * m, &phi));
+  hipLaunchKernelGGL(k_gather_cols, dim3(launch_grid((int64_t)n * m)), dim3(256), 0, st, n, m, (const c64*)T, n,
+                     (const int32_t*)perm, Up, n);
+  hipLaunchKernelGGL(k_gather_cols, dim3(launch_grid((int64_t)n * m)), dim3(256), 0, st, n, m, (const c64*)W, n,
+                     (const int32_t*)perm, Wp, n);
+  CBS_HIP(hipGetLastError());
+  CBS_TRY(small_gemm(n, m, n, Tl, n, false, Wp, n, TW, n, nullptr, nullptr, st));
+  // Bred = Up^H TW diag(1/sigma)
+  std::vector<double> inv(m);
+  for (int i = 0; i < m; ++i) inv[i] = 1.0 / hsig[i];
+  double* dinv = nullptr;
+  CBS_TRY(ws_get(ws, "hk.inv", (size_t)m, &dinv));
+  CBS_HIP(hipMemcpyAsync(dinv, inv.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
+  CBS_TRY(small_gemm(m, m, n, Up, n, true, TW, n, Bred, m, dinv, nullptr, st));
+  CBS_TRY(eig(s, m, Bred, m, tau, phi, m, info, st));
+
+  std::vector<c64> cand;
+  c64* basis = nullptr;   // N x ncand candidate vectors (not normalised)
+  int ncand = 0;
+  const int64_t capv = std::max<int64_t>(2 * m, 1);
+  CBS_TRY(ws_get(ws, "ex.vec", (size_t)capv * N, &basis));
+  if (prm->extraction == CBS_HANKEL) {
+    c64* coef = nullptr;
+    CBS_TRY(ws_get(ws, "hk.coef", (size_t)n * m, &coef));
+    hipLaunchKernelGGL(k_scale_rows_gemm, dim3(launch_grid((int64_t)n * m)), dim3(256), 0, st, n, m, (const c64*)Wp,
+                       (const double*)sig, (const c64*)phi, coef);
+    CBS_HIP(hipGetLastError());
+    CBS_TRY(tall_gemm(N, n, m, S, N, coef, n, basis, N, st));
+    cand.resize(m);
+    CBS_HIP(hipMemcpyAsync(cand.data(), tau, m * sizeof(c64), hipMemcpyDeviceToHost, st));
+    ncand = m;
+  } else {
+    // --- Rayleigh-Ritz on Q = orth(S_{<M} W1): shifted Cholesky QR, then two plain passes
+    c64 *Qa = nullptr, *Qb = nullptr, *G = nullptr, *Ri = nullptr;
+    CBS_TRY(ws_get(ws, "rr.Qa", (size_t)m * N, &Qa));
+    CBS_TRY(ws_get(ws, "rr.Qb", (size_t)m * N, &Qb));
+    CBS_TRY(ws_get(ws, "rr.G", (size_t)m * m, &G));
+    CBS_TRY(ws_get(ws, "rr.Ri", (size_t)m * m, &Ri));
+    CBS_TRY(tall_gemm(N, n, m, S, N, Wp, n, Qa, N, st));
+    for (int pass = 0; pass < 3; ++pass) {
+      CBS_TRY(gram(s, N, m, Qa, N, m, Qa, N, G, m, st));
+      double shift = 0;
+      if (pass == 0) {
+        std::vector<c64> hg((size_t)m * m);
+        CBS_HIP(hipMemcpyAsync(hg.data(), G, hg.size() * sizeof(c64), hipMemcpyDeviceToHost, st));
+        CBS_HIP(hipStreamSynchronize(st));
+        double tr = 0;
+        for (int i = 0; i < m; ++i) tr += hg[(size_t)i * m + i].x;
+        shift = 11.0 * ((double)N * m + (double)m * (m + 1)) * 1.1102230246251565e-16 * tr;
+      }
+      CBS_TRY(chol_inv(m, G, m, shift, Ri, info, st));
+      CBS_TRY(tall_gemm(N, m, m, Qa, N, Ri, m, Qb, N, st));
+      std::swap(Qa, Qb);
+    }
+    // projected blocks A0 = Q^H (H0-E) Q, A+ = Q^H H+ Q, A- = Q^H H- Q
+    c64 *HQ = nullptr, *A3 = nullptr;
+    CBS_TRY(ws_get(ws, "rr.HQ", (size_t)3 * m * N, &HQ));
+    CBS_TRY(ws_get(ws, "rr.A3", (size_t)3 * m * m, &A3));
+    std::vector<c64> one(m, make_double2(1, 0)), zero(m, make_double2(0, 0));
+    CBS_TRY(apply_parts_dev(s, E, m, one.data(), zero.data(), zero.data(), Qa, HQ, st));
+    CBS_TRY(apply_parts_dev(s, E, m, zero.data(), one.data(), zero.data(), Qa, HQ + (size_t)m * N, st));
+    CBS_TRY(apply_parts_dev(s, E, m, zero.data(), zero.data(), one.data(), Qa, HQ + (size_t)2 * m * N, st));
+    for (int p = 0; p < 3; ++p)
+      CBS_TRY(gram(s, N, m, Qa, N, m, HQ + (size_t)p * m * N, N, A3 + (size_t)p * m * m, m, st));
+    const int n2 = 2 * m;
+    c64 *X = nullptr, *Bl = nullptr, *th = nullptr, *vv = nullptr;
+    CBS_TRY(ws_get(ws, "rr.X", (size_t)n2 * n2, &X));
+    CBS_TRY(ws_get(ws, "rr.B", (size_t)n2 * n2, &Bl));
+    CBS_TRY(ws_get(ws, "rr.th", (size_t)n2, &th));
+    CBS_TRY(ws_get(ws, "rr.vv", (size_t)n2 * n2, &vv));
+    const c64 sft = make_double2(0.83 * cos(0.7654), 0.83 * sin(0.7654));
+    hipLaunchKernelGGL(k_linearize, dim3(launch_grid((int64_t)n2 * n2)), dim3(256), 0, st, m, (const c64*)A3,
+                       (const c64*)(A3 + (size_t)m * m), (const c64*)(A3 + (size_t)2 * m * m), sft, X, Bl);
+    CBS_HIP(hipGetLastError());
+    CBS_TRY(lu_solve(n2, X, n2, Bl, n2, n2, info, st));
+    CBS_TRY(eig(s, n2, Bl, n2, th, vv, n2, info, st));
+    std::vector<c64> hth(n2);
+    CBS_HIP(hipMemcpyAsync(hth.data(), th, n2 * sizeof(c64), hipMemcpyDeviceToHost, st));
+    CBS_HIP(hipStreamSynchronize(st));
+    double thmax = 0;
+    for (auto& t : hth) thmax = std::max(thmax, sqrt(cabs2<double>(t)));
+    // keep finite eigenvalues inside (a slightly widened) annulus; x = top half of v
+    std::vector<int32_t> keep;
+    const double lmin = prm->lambda_min;
+    for (int i = 0; i < n2; ++i) {
+      if (!(sqrt(cabs2<double>(hth[i])) > 1e-13 * thmax)) continue;
+      const c64 lam = cadd<double>(sft, cdiv<double>(make_double2(1, 0), hth[i]));
+      const double a = sqrt(cabs2<double>(lam));
+      if (a > lmin * (1 - 1e-9) && a < (1 + 1e-9) / lmin) {
+        keep.push_back(i);
+        cand.push_back(lam);
+      }
+    }
+    ncand = (int)keep.size();
+    if (ncand > 0) {
+      int32_t* dkeep = nullptr;
+      c64* Xt = nullptr;
+      CBS_TRY(ws_get(ws, "rr.keep", (size_t)ncand, &dkeep));
+      CBS_TRY(ws_get(ws, "rr.Xt", (size_t)m * ncand, &Xt));
+      CBS_HIP(hipMemcpyAsync(dkeep, keep.data(), ncand * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_gather_cols, dim3(launch_grid((int64_t)m * ncand)), dim3(256), 0, st, m, ncand,
+                         (const c64*)vv, n2, (const int32_t*)dkeep, Xt, m);
+      CBS_HIP(hipGetLastError());
+      CBS_TRY(tall_gemm(N, m, ncand, Qa, N, Xt, m, basis, N, st));
+    }
+  }
+  if (ncand == 0) return CBS_OK;
+  // --- normalise, residuals ||P(lambda) psi||, annulus, sorting
+  double* norms = nullptr;
+  c64* psi = nullptr;
+  c64* Ppsi = nullptr;
+  CBS_TRY(ws_get(ws, "ex.norm", (size_t)ncand, &norms));
+  CBS_TRY(ws_get(ws, "ex.psi", (size_t)ncand * N, &psi));
+  CBS_TRY(ws_get(ws, "ex.Ppsi", (size_t)ncand * N, &Ppsi));
+  CBS_TRY(vec_norms(N, ncand, basis, N, norms, true, psi, N, st));
+  std::vector<c64> c0(ncand, make_double2(1, 0)), cm(ncand);
+  for (int i = 0; i < ncand; ++i) cm[i] = cdiv<double>(make_double2(1, 0), cand[i]);
+  CBS_TRY(apply_parts_dev(s, E, ncand, c0.data(), cand.data(), cm.data(), psi, Ppsi, st));
+  std::vector<double> rn(ncand);
+  CBS_TRY(vec_norms(N, ncand, Ppsi, N, norms, false, nullptr, 0, st));
+  CBS_HIP(hipMemcpyAsync(rn.data(), norms, ncand * sizeof(double), hipMemcpyDeviceToHost, st));
+  int32_t hinfo[4];
+  CBS_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+  CBS_HIP(hipStreamSynchronize(st));
+  if (hinfo[0] == 1) {
+    set_error("QR iteration of the reduced eigenproblem did not converge");
+    return CBS_ENOCONV;
+  }
+  // operator scale for the spurious-pair filter
+  double cs = std::fabs(s->fd[0]);
+  for (int m2 = 1; m2 <= s->p; ++m2) cs += 2 * std::fabs(s->fd[m2]);
+  const double pscale = 3.0 * 0.5 * cs / (s->h * s->h) + std::fabs(E) + 10.0;
+  const double keep_tol = (prm->extraction == CBS_HANKEL ? 1e-2 : 1e-6) * pscale;
+  std::vector<int> idx;
+  const double lmin = prm->lambda_min;
+  for (int i = 0; i < ncand; ++i) {
+    const double a = sqrt(cabs2<double>(cand[i]));
+    if (!(a > lmin && a < 1.0 / lmin)) continue;   // strict annulus (Eq. 5)
+    if (!(rn[i] <= keep_tol)) continue;
+    idx.push_back(i);
+  }
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+    const double la = std::fabs(std::log(sqrt(cabs2<double>(cand[a])))), lb = std::fabs(std::log(sqrt(cabs2<double>(cand[b]))));
+    if (la != lb) return la < lb;
+    return atan2(cand[a].y, cand[a].x) < atan2(cand[b].y, cand[b].x);
+  });
+  out.lam.resize(idx.size());
+  out.res.resize(idx.size());
+  CBS_TRY(ws_get(ws, "ex.out", std::max<size_t>(idx.size(), 1) * N, &out.vecs));
+  for (size_t k = 0; k < idx.size(); ++k) {
+    out.lam[k] = cand[idx[k]];
+    out.res[k] = rn[idx[k]];
+    CBS_HIP(hipMemcpyAsync(out.vecs + k * N, psi + (size_t)idx[k] * N, N * sizeof(c64), hipMemcpyDeviceToDevice, st));
+  }
+  CBS_HIP(hipStreamSynchronize(st));
+  return CBS_OK;
+}
+
+int32_t store_last(cbs_system* s, double E, const Extracted& ex, hipStream_t st) {
+  LastSolve& L = s->last;
+  const size_t cnt = ex.lam.size();
+  if (L.cap < cnt) {
+    if (L.vecs) (void)hipFree(L.vecs);
+    L.vecs = nullptr;
+    L.cap = 0;
+    if (hipMalloc(&L.vecs, std::max<size_t>(cnt, 1) * s->N * sizeof(c64)) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("allocation for the stored eigenpairs failed");
+      return CBS_ENOMEM;
+    }
+    L.cap = cnt;
+  }
+  L.n = (int32_t)cnt;
+  L.E = E;
+  L.lambda = ex.lam;
+  if (cnt) CBS_HIP(hipMemcpyAsync(L.vecs, ex.vecs, cnt * s->N * sizeof(c64), hipMemcpyDeviceToDevice, st));
+  return CBS_OK;
+}
+
+}  // namespace cbs
+
+using namespace cbs;
+
+extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, const void* V, int32_t max_eigs,
+                             double* lambda, double* resid, void* vecs, int32_t* n_eigs, cbs_info* info,
+                             void* stream) {
+  if (!s || !V || max_eigs < 0 || (max_eigs > 0 && !lambda) || !n_eigs) {
+    set_error("cbs_solve: bad argument");
+    return CBS_EINVAL;
+  }
+  CBS_TRY(check_params(prm, true));
+  CBS_HIP(hipSetDevice(s->device));
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<c64> z1, w1, z2, w2;
+  quadrature(prm->lambda_min, prm->n_q, z1, w1, z2, w2);
+  NodeSolve ns;
+  CBS_TRY(solve_nodes(s, E, z1.data(), prm->n_q, prm->n_rhs, (const c64*)V, prm, st, ns));
+  Extracted ex;
+  double tmom = 0;
+  auto t0 = std::chrono::steady_clock::now();
+  CBS_TRY(extract(s, E, prm, (const c64*)V, ns.Y, st, ex, &tmom));
+  auto t1 = std::chrono::steady_clock::now();
+  CBS_TRY(store_last(s, E, ex, st));
+  const int cnt = (int)ex.lam.size();
+  *n_eigs = cnt;
+  bool noconv = false, brk = false;
+  double mx = 0, sum = 0;
+  int im = 0;
+  for (int r = 0; r < ns.nruns; ++r) {
+    noconv = noconv || (ns.status[r] != RUN_DONE && ns.status[r] != RUN_HALTED);
+    brk = brk || ns.status[r] == RUN_BREAKDOWN;
+    mx = std::max(mx, std::max(ns.relres[2 * r], ns.relres[2 * r + 1]));
+    im = std::max(im, ns.iters[r]);
+    sum += ns.iters[r];
+  }
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->rank = ex.rank;
+    info->n_eigs = cnt;
+    info->iters_max = im;
+    info->iters_mean = sum / std::max(1, ns.nruns);
+    info->max_solve_resid = mx;
+    double er = 0;
+    for (double r : ex.res) er = std::max(er, r);
+    info->max_eig_resid = er;
+    info->sigma_first = ex.sig1;
+    info->sigma_ratio = ex.sig_ratio;
+    info->t_solve_ms = ns.ms;
+    info->t_moments_ms = tmom;
+    info->t_extract_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() - tmom;
+    info->matvecs = (int64_t)(2 * sum);
+    info->refine_steps = 0;
+    info->stencil_launches = ns.prof_launches;
+    info->stencil_ms = ns.prof_ms;
+    info->stencil_bytes = ns.prof_bytes;
+  }
+  if (cnt > max_eigs) {
+    set_error("cbs_solve: %d eigenvalues, output holds %d", cnt, max_eigs);
+    return CBS_ETOOMANY;
+  }
+  for (int k = 0; k < cnt; ++k) {
+    lambda[2 * k] = ex.lam[k].x;
+    lambda[2 * k + 1] = ex.lam[k].y;
+    if (resid) resid[k] = ex.res[k];
+  }
+  if (vecs && cnt)
+    CBS_HIP(hipMemcpyAsync(vecs, ex.vecs, (size_t)cnt * s->N * sizeof(c64), hipMemcpyDeviceToDevice, st));
+  CBS_HIP(hipStreamSynchronize(st));
+  if (brk) {
+    set_error("cbs_solve: BiCG breakdown in some runs");
+    return CBS_EBREAKDOWN;
+  }
+  if (noconv) {
+    set_error("cbs_solve: some linear solves missed the tolerance");
+    return CBS_ENOCONV;
+  }
+  if (ex.rank >= prm->n_rhs * prm->n_mom) {
+    set_error("cbs_solve: Hankel rank %d reached L*M; enlarge L or M", ex.rank);
+    return CBS_ERANK;
+  }
+  return CBS_OK;
+}

@@ -27,7 +27,6 @@ struct StArgs {
   int64_t N;
   R kin;      // -1/(2 h^2)
   R c[5];     // c_0..c_p
-  R E;
   const R* vloc;
   const Pair<R>* rin;
   const Pair<R>* pold;
@@ -38,10 +37,11 @@ struct StArgs {
   const double2* beta;
   const double2* xcoef;
   const int32_t* status;
+  int32_t need_status;
   double2* sig_part;
 };
 
-__device__ __forceinline__ double2 wave_sum(double2 v) {
+__device__ __forceinline__ double2 wave_sum2(double2 v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     v.x += __shfl_xor(v.x, off, 64);
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
   if (lb >= a.nlogical) return;
   const int run = lb / a.ntiles;
   const int tile = lb - run * a.ntiles;
-  if (BICG && a.status != nullptr && a.status[run] != RUN_ACTIVE) return;
+  if (a.status != nullptr && a.status[run] != a.need_status) return;
 
   const int nx = a.nx, ny = a.ny, nz = a.nz, TY = a.ty;
   const int tid = threadIdx.x;
@@ -82,6 +82,7 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
                 cma = ccast<R, double>(cf.c[2]);
   const cplx<R> c0b = ccast<R, double>(cf.c[3]), cpb = ccast<R, double>(cf.c[4]),
                 cmb = ccast<R, double>(cf.c[5]);
+  const R Erun = (R)cf.E;
   cplx<R> ba = mkc<R>(0, 0), bb = ba, xa = ba, xb = ba;
   bool do_x = false;
   if (BICG) {
@@ -167,7 +168,7 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
           sa = cfma_r<R>(sa, cj, cadd<R>(cadd<R>(l.a, rr.a), cadd<R>(dn.a, up.a)));
           sb = cfma_r<R>(sb, cj, cadd<R>(cadd<R>(l.b, rr.b), cadd<R>(dn.b, up.b)));
         }
-        const R vd = a.vloc[tx + (int64_t)nx * y + plane * m] - a.E;
+        const R vd = a.vloc[tx + (int64_t)nx * y + plane * m] - Erun;
         sa = cfma_r<R>(cscale<R>(sa, a.kin), vd, v.a);
         sb = cfma_r<R>(cscale<R>(sb, a.kin), vd, v.b);
         inb.a = cmul<R>(c0a, sa);
@@ -222,7 +223,7 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
   }
 
   if (BICG) {
-    sig = wave_sum(sig);
+    sig = wave_sum2(sig);
     const int lane = tid & 63, wv = tid >> 6;
     if (lane == 0) red[wv] = sig;
     __syncthreads();
@@ -286,7 +287,6 @@ int32_t launch_stencil(const cbs_system* s, bool bicg, const StencilLaunch& l, i
   a.N = s->N;
   a.kin = (R)(-0.5 / (s->h * s->h));
   for (int i = 0; i < 5; ++i) a.c[i] = (R)s->fd[i];
-  a.E = (R)l.E;
   a.vloc = std::is_same<R, double>::value ? (const R*)s->vloc64 : (const R*)s->vloc32;
   a.rin = (const Pair<R>*)l.rin;
   a.pold = (const Pair<R>*)l.pold;
@@ -297,6 +297,7 @@ int32_t launch_stencil(const cbs_system* s, bool bicg, const StencilLaunch& l, i
   a.beta = l.beta;
   a.xcoef = l.xcoef;
   a.status = l.status;
+  a.need_status = l.need_status;
   a.sig_part = l.sig_part;
   switch (s->p) {
     case 1: return bicg ? launch_p<R, 1, true>(s, a, st) : launch_p<R, 1, false>(s, a, st);

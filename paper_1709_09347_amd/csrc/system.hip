@@ -210,6 +210,7 @@ int32_t apply_parts_dev(cbs_system* s, double E, int32_t n_vec, const double2* c
       hc[k].c[3 * h + 1] = ok ? cp[v] : make_double2(0, 0);
       hc[k].c[3 * h + 2] = ok ? cm[v] : make_double2(0, 0);
     }
+    hc[k].E = E;
   }
   CBS_HIP(hipMemcpyAsync(coef, hc.data(), nr * sizeof(RunCoef), hipMemcpyHostToDevice, st));
   CBS_TRY(launch_to_pairs<double>(s->N, n_vec, x, px, st));
@@ -218,7 +219,6 @@ int32_t apply_parts_dev(cbs_system* s, double E, int32_t n_vec, const double2* c
   l.rin = px;
   l.q = pq;
   l.coef = coef;
-  l.E = E;
   const int32_t ty = s->tile_y[0] ? s->tile_y[0] : default_tile_y(s, sizeof(Pair<double>));
   CBS_TRY(launch_stencil<double>(s, false, l, ty, st));
   if (s->proj.n_atoms > 0) {
@@ -260,6 +260,7 @@ static int32_t apply_z(cbs_system* s, double E, int32_t n_vec, const double* z, 
       hc[k].c[3 * h + 1] = make_double2(zr, zi);
       hc[k].c[3 * h + 2] = make_double2(zr / d, -zi / d);
     }
+    hc[k].E = E;
   }
   CBS_HIP(hipMemcpyAsync(coef, hc.data(), nr * sizeof(RunCoef), hipMemcpyHostToDevice, st));
   CBS_TRY(launch_to_pairs<R>(s->N, n_vec, x, px, st));
@@ -268,7 +269,6 @@ static int32_t apply_z(cbs_system* s, double E, int32_t n_vec, const double* z, 
   l.rin = px;
   l.q = pq;
   l.coef = coef;
-  l.E = E;
   const int32_t ty = s->tile_y[std::is_same<R, double>::value ? 0 : 1];
   CBS_TRY(launch_stencil<R>(s, false, l, ty ? ty : default_tile_y(s, sizeof(Pair<R>)), st));
   if (s->proj.n_atoms > 0) {
