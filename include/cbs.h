@@ -144,6 +144,11 @@ void cbs_system_destroy(cbs_system* sys);
 /* Replace V_loc (host [N] double); keeps projectors and workspace. */
 int32_t cbs_system_set_vloc(cbs_system* sys, const double* v_loc);
 int64_t cbs_system_npoints(const cbs_system* sys);
+/* Stencil tiling: tile_y[0] (complex128) and tile_y[1] (complex64) full-x rows per
+ * workgroup, and the autotuner's timings ("" before the first solve tuned them;
+ * CBS_AUTOTUNE=0 keeps the heuristic defaults).  The string lives until the next
+ * solve on sys. */
+const char* cbs_system_tiling(const cbs_system* sys, int32_t* tile_y);
 
 void cbs_params_default(cbs_params* p);
 
@@ -199,14 +204,21 @@ int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, int32_t n_E
                           int32_t* n_eigs, cbs_info* info, void* stream);
 
 /* ---- adjoint --------------------------------------------------------
- * d lambda_i / d V_loc(r) for eigenpairs sel[k] (indices into the last
+ * d lambda_i / d V_loc(r) for eigenpairs sel[k] (host indices into the last
  * cbs_solve's output) = -conj(y_i(r)) x_i(r) / (y_i^H P'(lambda_i) x_i) with
  * P'(lambda) = H+ - lambda^{-2} H- and y_i the eigenvector of the pair
- * partner 1/conj(lambda_i) (P(lambda)^H = P(1/conj lambda), Sec. 3.2).
- * out: device [n_sel][N] complex128.  CBS_EINVAL if no solve is stored, an
- * index is out of range, or a selected eigenvalue has no simple partner. */
+ * partner 1/conj(lambda_i), which is a left eigenvector of lambda_i because
+ * P(lambda)^H = P(1/conj lambda) (Sec. 3.2): the inner-circle (dual) solves
+ * already carry it, no extra solve is made.
+ * out: device [n_sel][N] complex128 (may be NULL).  If weights (host
+ * [2*n_sel], complex g_k) and vjp (device [N] double) are given, also writes
+ * the vector-Jacobian product vjp(r) = sum_k Re(g_k conj(d lambda_k/d V(r))),
+ * the gradient of a real loss whose conjugate-Wirtinger derivative with
+ * respect to lambda_k is g_k (PyTorch's convention for complex outputs).
+ * CBS_EINVAL if no solve is stored, an index is out of range, or a selected
+ * eigenvalue has no simple partner (degenerate within 1e-7 relative). */
 int32_t cbs_grad_vloc(cbs_system* sys, int32_t n_sel, const int32_t* sel, void* out,
-                      void* stream);
+                      const double* weights, void* vjp, void* stream);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,7 @@ CBS_RR, CBS_HANKEL = 0, 1
 # every function the header declares
 EXPORTS = [
     "cbs_strerror", "cbs_last_error", "cbs_system_create", "cbs_system_destroy",
-    "cbs_system_set_vloc", "cbs_system_npoints", "cbs_params_default", "cbs_apply",
+    "cbs_system_set_vloc", "cbs_system_npoints", "cbs_system_tiling", "cbs_params_default", "cbs_apply",
     "cbs_apply_parts", "cbs_bicg", "cbs_solve", "cbs_solve_batched", "cbs_grad_vloc",
 ]
 
@@ -99,6 +99,8 @@ def lib():
         L.cbs_system_set_vloc.argtypes = [vp, vp]
         L.cbs_system_npoints.restype = i64
         L.cbs_system_npoints.argtypes = [vp]
+        L.cbs_system_tiling.restype = ctypes.c_char_p
+        L.cbs_system_tiling.argtypes = [vp, vp]
         L.cbs_params_default.restype = None
         L.cbs_params_default.argtypes = [ctypes.POINTER(Params)]
         L.cbs_apply.restype = i32
@@ -115,7 +117,7 @@ def lib():
         L.cbs_solve_batched.argtypes = [i32, vp, i32, vp, ctypes.POINTER(Params), vp, i32, vp, vp,
                                         vp, vp]
         L.cbs_grad_vloc.restype = i32
-        L.cbs_grad_vloc.argtypes = [vp, i32, vp, vp, vp]
+        L.cbs_grad_vloc.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         _LIB = L
     return _LIB
 
@@ -195,6 +197,12 @@ class System:
         except Exception:
             pass
 
+    def tiling(self):
+        """(tile_y complex128, tile_y complex64, autotuner log)."""
+        ty = np.zeros(2, dtype=np.int32)
+        log = lib().cbs_system_tiling(self.handle, ty.ctypes.data).decode()
+        return int(ty[0]), int(ty[1]), log
+
     def set_vloc(self, v_loc):
         v = np.ascontiguousarray(np.asarray(v_loc, dtype=np.float64))
         _check(lib().cbs_system_set_vloc(self.handle, v.ctypes.data), "cbs_system_set_vloc")
@@ -270,12 +278,58 @@ class System:
         return lamc, (vecs[:m] if vecs is not None else None), res[:m].copy(), info, rc
 
     def grad_vloc(self, sel: Sequence[int], stream=None):
+        """d lambda_k / d V_loc for the eigenpairs sel of the last solve: [len(sel), N] complex128."""
         import torch
         s = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
         out = torch.empty((len(s), self.n), dtype=torch.complex128, device=f"cuda:{self.device}")
-        _check(lib().cbs_grad_vloc(self.handle, len(s), s.ctypes.data, _ptr(out), _stream(stream)),
-               "cbs_grad_vloc")
+        _check(lib().cbs_grad_vloc(self.handle, len(s), s.ctypes.data, _ptr(out), None, None,
+                                   _stream(stream)), "cbs_grad_vloc")
         return out
+
+    def vjp_vloc(self, sel: Sequence[int], weights, stream=None):
+        """sum_k Re(g_k conj(d lambda_k / d V_loc)) for host weights g: [N] float64 tensor."""
+        import torch
+        s = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
+        w = _host_c128(weights)
+        out = torch.empty(self.n, dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(lib().cbs_grad_vloc(self.handle, len(s), s.ctypes.data, None, w.ctypes.data, _ptr(out),
+                                   _stream(stream)), "cbs_grad_vloc")
+        return out
+
+
+def _autograd():
+    import torch
+
+    class CbsEig(torch.autograd.Function):
+        """lambda_sel(V_loc): eigenvalues of the annulus as a differentiable function of V_loc.
+
+        forward solves (cbs_solve) with the given potential; backward calls the adjoint
+        kernel (cbs_grad_vloc) with the incoming gradient as weights.  ``select`` maps the
+        sorted eigenvalues (numpy) to the indices to return.
+        """
+
+        @staticmethod
+        def forward(ctx, v_loc, system, E, V, params, select):
+            system.set_vloc(v_loc.detach().cpu().numpy())
+            lam, _, _, _, _ = system.solve(E, V, params, want_vectors=False)
+            sel = np.asarray(select(lam), dtype=np.int32)
+            ctx.system, ctx.sel, ctx.vdev = system, sel, v_loc.device
+            return torch.from_numpy(lam[sel].copy())
+
+        @staticmethod
+        def backward(ctx, grad):
+            g = grad.detach().cpu().numpy().astype(np.complex128)
+            v = ctx.system.vjp_vloc(ctx.sel, g)
+            return v.to(ctx.vdev), None, None, None, None, None
+
+    return CbsEig
+
+
+def cbs_eig(v_loc, system: "System", E: float, V, params: Optional[Params] = None, select=None):
+    """Differentiable eigenvalues lambda(V_loc) (see CbsEig); default: all of them."""
+    params = params or default_params()
+    select = select or (lambda lam: np.arange(len(lam)))
+    return _autograd().apply(v_loc, system, E, V, params, select)
 
 
 def solve_batched(systems: List[System], energies, Vs, params: Optional[Params] = None,

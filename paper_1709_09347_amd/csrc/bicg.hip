@@ -1,52 +1,59 @@
-// Step 1 of the Sakurai-Sugiura method (paper Sec. 3.1, Eq. 8 and Sec. 3.2,
-// Eqs. 9-11): BiCG on P(z_j) y = v for every quadrature node and right-hand side,
-// whose dual recurrences solve P(z_j)^H yt = v, i.e. the inner-circle systems
-// (P(z)^H = P(1/conj z)).  Every run (node, right-hand side) is a batch entry of the
-// same kernel launches (the paper's top and middle layers of parallelism).
+// Step 1 of the Sakurai-Sugiura method (paper Sec. 3.1, Eq. 8 and Sec. 3.2, Eqs. 9-11):
+// BiCG on P(z_j) y = v for every quadrature node and right-hand side, whose dual
+// recurrences solve P(z_j)^H yt = v, i.e. the inner-circle systems (P(z)^H = P(1/conj z)).
+// Every run (node, right-hand side, energy) is a batch entry of the same kernel launches
+// (the paper's top and middle layers of parallelism become one batch dimension).
 //
-// Per iteration (all runs at once):
+// Per iteration, for every precision phase that has runs:
 //   A   stencil: p = r + beta p_old (dual conj(beta)), q = local part of P p,
 //       x += xcoef p_old, local part of sigma = pt^H q
 //   bra projector coefficients of p, nonlocal part of sigma
+// then
 //   S1  alpha = rho / sigma
-//   B   r -= alpha (q + ket), rt -= conj(alpha) (qt + ket); rho, ||r||, ||rt||
-//   S2  beta = rho_new / rho; convergence test on the recursive residuals
-//   RU  reliable update (residual replacement) for the runs S2 marked: the
-//       iterate is accumulated into the complex128 solution y, the true residual
-//       v - P y is recomputed in complex128 and replaces r (the search direction is
-//       kept, so the Krylov space is not restarted).  In the complex128 path S2 only
-//       marks runs whose recursive residual met tol (a final check); in the
-//       complex64 path it also marks runs whose residual fell by `ru_factor` since
-//       the last replacement: that is the FP64 iterative refinement of the inner
-//       single-precision solve.
-//   S3  decisions on the true residual (done / continue), count of active runs.
-// The iteration sequence is captured once into a HIP graph of `chunk` iterations and
-// replayed until no run is active.
+//   B   r -= alpha (q + ket), rt -= conj(alpha) (qt + ket); rho, ||r||^2, ||rt||^2
+//   S2  beta = rho_new / rho; tests on the recursive residuals
+//   RU  residual replacement for the runs S2 marked: the iterate is accumulated into
+//       the complex128 solution y, the true residual v - P y is recomputed in complex128
+//       and replaces r; the search direction is kept, so the Krylov space is not
+//       restarted.
+//   S3  decisions on the true residual (done / continue / change phase), active counts.
+// Precision (mixed mode): runs start with complex64 vectors; a replacement is triggered
+// whenever the recursive residual has dropped by `ru_factor` since the last one (the
+// FP64 iterative refinement of the single-precision recurrence); once the true residual
+// is below `switch_tol` the run's search direction is widened to complex128 and the
+// same recurrence finishes in complex128 (the complex64 recurrence converges almost as
+// fast as the complex128 one down to ~1e-4 and slows down beyond).  FP64 mode starts in
+// the complex128 phase, where S2 only marks runs whose recursive residual met tol.
+// The iteration is captured once into a HIP graph of `chunk` iterations and replayed
+// until no run is active.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <string>
 #include <type_traits>
 #include <vector>
 
-#include "cbs_internal.hpp"
 #include "bicg.hpp"
+#include "cbs_internal.hpp"
 
 namespace cbs {
 
+static int32_t grid8(int64_t nlogical) { return (int32_t)((nlogical + 7) / 8 * 8); }
+
 // ------------------------------------------------------------------ pointwise kernels
 template <typename T>
-__global__ void k_bicg_init(int64_t N, int32_t nruns, int32_t L, const double2* V, Pair<T>* R,
+__global__ void k_bicg_init(int64_t N, int32_t nruns, int32_t L, const double2* V, const double2* Vd, Pair<T>* R,
                             Pair<T>* P0, Pair<T>* P1, Pair<T>* X, Pair<double>* Y) {
   const int64_t total = N * nruns;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t run = g / N, n = g - run * N;
     const double2 v = V[(run % L) * N + n];
+    const double2 vd = Vd[(run % L) * N + n];
     Pair<T> r;
     r.a = mkc<T>((T)v.x, (T)v.y);
-    r.b = r.a;
+    r.b = mkc<T>((T)vd.x, (T)vd.y);
     R[g] = r;
     Pair<T> z;
     z.a = mkc<T>(0, 0);
@@ -54,17 +61,19 @@ __global__ void k_bicg_init(int64_t N, int32_t nruns, int32_t L, const double2* 
     P0[g] = z;
     P1[g] = z;
     X[g] = z;
-    Pair<double> zd;
-    zd.a = make_double2(0, 0);
-    zd.b = zd.a;
-    Y[g] = zd;
+    if (Y != nullptr) {
+      Pair<double> zd;
+      zd.a = make_double2(0, 0);
+      zd.b = zd.a;
+      Y[g] = zd;
+    }
   }
 }
 
 // rho = rt^H r, ||r||^2, ||rt||^2 partial sums of the initial residual
 template <typename T>
-__global__ void __launch_bounds__(256) k_partials(int64_t N, int32_t nchunks, int32_t nlogical,
-                                                  const Pair<T>* R, double* part) {
+__global__ void __launch_bounds__(256) k_partials(int64_t N, int32_t nchunks, int32_t nlogical, const Pair<T>* R,
+                                                  double* part) {
   __shared__ double red[4][4];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   if (lb >= nlogical) return;
@@ -88,15 +97,15 @@ __global__ void __launch_bounds__(256) k_partials(int64_t N, int32_t nchunks, in
   if (tid < 4) part[((int64_t)run * nchunks + ch) * 4 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
-// Reliable update, first half: x += xcoef p (the pending update), y += x, x = 0.
+// Residual replacement, first half: x += xcoef p (the pending update), y += x, x = 0.
 template <typename T>
-__global__ void __launch_bounds__(256) k_ru_pre(int64_t N, int32_t nchunks, int32_t nlogical,
-                                                const int32_t* status, const double2* xcoef,
-                                                const Pair<T>* P, Pair<T>* X, Pair<double>* Y) {
+__global__ void __launch_bounds__(256) k_ru_pre(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* status,
+                                                int32_t need, const double2* xcoef, const Pair<T>* P, Pair<T>* X,
+                                                Pair<double>* Y) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   if (lb >= nlogical) return;
   const int run = lb / nchunks, ch = lb - run * nchunks;
-  if (status[run] != RUN_RU) return;
+  if (status[run] != need) return;
   const int64_t chunk = (N + nchunks - 1) / nchunks;
   const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
   const double2 xc = xcoef[run];
@@ -118,24 +127,26 @@ __global__ void __launch_bounds__(256) k_ru_pre(int64_t N, int32_t nchunks, int3
   }
 }
 
-// Reliable update, second half: r = v - P y in complex128 (q64 holds the local part,
-// the ket adds the projectors), written back as the working residual.
+// Residual replacement, second half: r = v - P y in complex128 (Q64 holds the local
+// part, the ket adds the projectors); written as the working residual R (precision T)
+// and, when R64 is given, also in complex128 (needed when the run changes phase).
 template <typename T>
-__global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int32_t nlogical,
-                                                 int32_t L, int32_t n_atoms, const int32_t* status,
-                                                 const double2* V, const Pair<double>* Q64,
+__global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int32_t nlogical, int32_t L,
+                                                 int32_t n_atoms, const int32_t* status, int32_t need,
+                                                 const double2* V, const double2* Vd, const Pair<double>* Q64,
                                                  const Pair<double>* KT64, const int32_t* pt_off,
-                                                 const int32_t* pt_key, const double* pt_u,
-                                                 Pair<T>* R, double* part) {
+                                                 const int32_t* pt_key, const double* pt_u, Pair<T>* R,
+                                                 Pair<double>* R64, double* part) {
   __shared__ double red[4][4];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   if (lb >= nlogical) return;
   const int run = lb / nchunks, ch = lb - run * nchunks;
-  if (status[run] != RUN_RU) return;
+  if (status[run] != need) return;
   const int64_t chunk = (N + nchunks - 1) / nchunks;
   const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double2* v = V + (int64_t)(run % L) * N;
+  const double2* vdual = Vd + (int64_t)(run % L) * N;
   double s[4] = {0, 0, 0, 0};
   for (int64_t n = lo + tid; n < hi; n += 256) {
     const int64_t g = (int64_t)run * N + n;
@@ -146,22 +157,44 @@ __global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int
       q.b = cadd<double>(q.b, k.b);
     }
     const double2 vv = v[n];
-    const double2 ra = csub<double>(vv, q.a), rb = csub<double>(vv, q.b);
+    Pair<double> r64;
+    r64.a = csub<double>(vv, q.a);
+    r64.b = csub<double>(vdual[n], q.b);
     Pair<T> r;
-    r.a = ccast<T, double>(ra);
-    r.b = ccast<T, double>(rb);
+    r.a = ccast<T, double>(r64.a);
+    r.b = ccast<T, double>(r64.b);
     R[g] = r;
+    if (R64 != nullptr) R64[g] = r64;
     const cplx<T> rho = cmulc<T>(r.b, r.a);
     s[0] += (double)rho.x;
     s[1] += (double)rho.y;
-    s[2] += cabs2<double>(ra);
-    s[3] += cabs2<double>(rb);
+    s[2] += cabs2<double>(r64.a);
+    s[3] += cabs2<double>(r64.b);
   }
   for (int k = 0; k < 4; ++k) s[k] = wsum<double>(s[k]);
   if (lane == 0)
     for (int k = 0; k < 4; ++k) red[wv][k] = s[k];
   __syncthreads();
   if (tid < 4) part[((int64_t)run * nchunks + ch) * 4 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+}
+
+// Widen the search direction of runs that changed phase this iteration.
+__global__ void __launch_bounds__(256) k_widen(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* conv,
+                                               const Pair<float>* Plo, Pair<double>* Phi) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (lb >= nlogical) return;
+  const int run = lb / nchunks, ch = lb - run * nchunks;
+  if (!conv[run]) return;
+  const int64_t chunk = (N + nchunks - 1) / nchunks;
+  const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
+  for (int64_t n = lo + threadIdx.x; n < hi; n += 256) {
+    const int64_t g = (int64_t)run * N + n;
+    const Pair<float> p = Plo[g];
+    Pair<double> d;
+    d.a = ccast<double, float>(p.a);
+    d.b = ccast<double, float>(p.b);
+    Phi[g] = d;
+  }
 }
 
 // ------------------------------------------------------------------ scalar kernels
@@ -173,8 +206,11 @@ __device__ __forceinline__ void sum_part(const double* part, int64_t off, int n,
     for (int k = 0; k < 4; ++k) s[k] += part[(off + c) * 4 + k];
 }
 
-__global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t nchunks,
-                                            const double* part, double ru_factor) {
+__device__ __forceinline__ bool is_active(int st) { return st == ST_ACT_LO || st == ST_ACT_HI; }
+__device__ __forceinline__ bool is_ru(int st) { return st == ST_RU_LO || st == ST_RU_HI; }
+
+__global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
+                                            int32_t start, double ru_factor) {
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
     double s[4];
     sum_part(part, (int64_t)run * nchunks, nchunks, s);
@@ -188,24 +224,26 @@ __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t 
     sc.nru[run] = 0;
     sc.brk[run] = 0;
     sc.halt[run] = 0;
-    sc.ru_thr[run] = ru_factor;
-    sc.relres[2 * run] = 1.0;
-    sc.relres[2 * run + 1] = 1.0;
-    sc.status[run] = (s[2] > 0) ? RUN_ACTIVE : RUN_DONE;
-    if (s[2] <= 0) {
-      sc.relres[2 * run] = 0;
-      sc.relres[2 * run + 1] = 0;
-    }
+    sc.conv[run] = 0;
+    sc.ru_thr[run] = (start == ST_ACT_LO) ? ru_factor : 0.0;
+    const bool zero = !(s[2] > 0);
+    sc.relres[2 * run] = zero ? 0.0 : 1.0;
+    sc.relres[2 * run + 1] = zero ? 0.0 : 1.0;
+    sc.status[run] = zero ? ST_DONE : start;
   }
 }
 
-__global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t ntiles, int32_t n_atoms,
-                                            const double2* sig_part, const double2* signl) {
+__global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t n_atoms, const double2* sig_lo,
+                                            int32_t nt_lo, const double2* sig_hi, int32_t nt_hi,
+                                            const double2* signl) {
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
-    if (sc.status[run] != RUN_ACTIVE) continue;
+    const int st = sc.status[run];
+    if (!is_active(st)) continue;
+    const double2* sp = (st == ST_ACT_LO) ? sig_lo : sig_hi;
+    const int nt = (st == ST_ACT_LO) ? nt_lo : nt_hi;
     double2 sg = make_double2(0, 0);
-    for (int t = 0; t < ntiles; ++t) {
-      const double2 v = sig_part[(int64_t)run * ntiles + t];
+    for (int t = 0; t < nt; ++t) {
+      const double2 v = sp[(int64_t)run * nt + t];
       sg.x += v.x;
       sg.y += v.y;
     }
@@ -216,7 +254,7 @@ __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t 
     }
     if (!(sg.x != 0.0 || sg.y != 0.0) || !finite2(sg)) {
       sc.brk[run] = 1;
-      sc.status[run] = RUN_RU;
+      sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
       sc.alpha[run] = make_double2(0, 0);
       sc.xcoef[run] = make_double2(0, 0);
       continue;
@@ -230,7 +268,8 @@ __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t 
 __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
                                             double tol, int32_t max_iter) {
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
-    if (sc.status[run] != RUN_ACTIVE) continue;
+    const int st = sc.status[run];
+    if (!is_active(st)) continue;
     double s[4];
     sum_part(part, (int64_t)run * nchunks, nchunks, s);
     const int it = sc.iters[run] + 1;
@@ -247,18 +286,19 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
     sc.beta[run] = bad ? make_double2(0, 0) : cdiv<double>(rn, ro);
     sc.rho_prev[run] = ro;
     sc.rho[run] = rn;
-    if (conv || bad || it >= max_iter || fmax(rr, rrt) < sc.ru_thr[run]) sc.status[run] = RUN_RU;
+    if (conv || bad || it >= max_iter || fmax(rr, rrt) < sc.ru_thr[run])
+      sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
   }
 }
 
 __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
-                                            double tol, int32_t max_iter, int32_t max_ru,
-                                            double ru_factor) {
-  __shared__ int cnt[4];
-  int active = 0;
+                                            double tol, int32_t max_iter, int32_t max_ru, double ru_factor,
+                                            double switch_tol) {
+  __shared__ int cnt[2][4];
+  int act_lo = 0, act_hi = 0;
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
     int st = sc.status[run];
-    if (st == RUN_RU) {
+    if (is_ru(st)) {
       double s[4];
       sum_part(part, (int64_t)run * nchunks, nchunks, s);
       const double vn = sc.vn2[run];
@@ -270,45 +310,66 @@ __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t 
       sc.xcoef[run] = make_double2(0, 0);
       const double2 rn = make_double2(s[0], s[1]);
       if (rr < tol && rrt < tol) {
-        st = RUN_DONE;
+        st = ST_DONE;
       } else if (sc.brk[run] || !finite2(rn) || !(rn.x != 0.0 || rn.y != 0.0)) {
-        st = RUN_BREAKDOWN;
+        st = ST_BREAKDOWN;
       } else if (sc.halt[run]) {
-        st = RUN_HALTED;
+        st = ST_HALTED;
       } else if (sc.iters[run] >= max_iter || nru >= max_ru) {
-        st = RUN_NOCONV;
+        st = ST_NOCONV;
       } else {
-        st = RUN_ACTIVE;
         sc.beta[run] = cdiv<double>(rn, sc.rho_prev[run]);
         sc.rho[run] = rn;
-        sc.ru_thr[run] = fmax(rr, rrt) * ru_factor;
+        if (st == ST_RU_LO && fmax(rr, rrt) <= switch_tol) {
+          st = ST_ACT_HI;   // finish the same recurrence in complex128
+          sc.conv[run] = 1;
+          sc.ru_thr[run] = 0.0;
+        } else if (st == ST_RU_LO) {
+          st = ST_ACT_LO;
+          sc.ru_thr[run] = fmax(rr, rrt) * ru_factor;
+        } else {
+          st = ST_ACT_HI;
+          sc.ru_thr[run] = 0.0;
+        }
       }
       sc.status[run] = st;
     }
-    active += (st == RUN_ACTIVE) ? 1 : 0;
+    act_lo += (st == ST_ACT_LO) ? 1 : 0;
+    act_hi += (st == ST_ACT_HI) ? 1 : 0;
   }
-  active = (int)wsum<double>((double)active);
-  if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = active;
+  act_lo = (int)wsum<double>((double)act_lo);
+  act_hi = (int)wsum<double>((double)act_hi);
+  if ((threadIdx.x & 63) == 0) {
+    cnt[0][threadIdx.x >> 6] = act_lo;
+    cnt[1][threadIdx.x >> 6] = act_hi;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) sc.n_active[0] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+  if (threadIdx.x == 0) {
+    sc.n_active[0] = cnt[0][0] + cnt[0][1] + cnt[0][2] + cnt[0][3];
+    sc.n_active[1] = cnt[1][0] + cnt[1][1] + cnt[1][2] + cnt[1][3];
+  }
 }
 
-// Half-of-the-nodes rule (paper Sec. 3.3): within every group of n_q*L runs, once
-// more than half of the nodes have all their right-hand sides converged, the
-// remaining runs stop.  Stopped runs still get their iterate accumulated (marked
-// for a last reliable update with an exhausted budget).
+__global__ void k_clear_conv(BicgScal sc, int32_t nruns) {
+  for (int run = threadIdx.x; run < nruns; run += blockDim.x) sc.conv[run] = 0;
+}
+
+// Half-of-the-nodes rule (paper Sec. 3.3): within every group of n_q*L runs, once more
+// than half of the nodes have all their right-hand sides converged, the remaining runs
+// stop (their iterate is still accumulated by a last replacement).
 __global__ void __launch_bounds__(256) k_half_stop(BicgScal sc, int32_t ngroups, int32_t n_q, int32_t L) {
   for (int g = threadIdx.x; g < ngroups; g += blockDim.x) {
     int done_nodes = 0;
     for (int j = 0; j < n_q; ++j) {
       bool all = true;
-      for (int l = 0; l < L; ++l) all = all && (sc.status[(g * n_q + j) * L + l] == RUN_DONE);
+      for (int l = 0; l < L; ++l) all = all && (sc.status[(g * n_q + j) * L + l] == ST_DONE);
       done_nodes += all ? 1 : 0;
     }
     if (2 * done_nodes > n_q) {
       for (int r = g * n_q * L; r < (g + 1) * n_q * L; ++r) {
-        if (sc.status[r] == RUN_ACTIVE) {
-          sc.status[r] = RUN_RU;
+        const int st = sc.status[r];
+        if (st == ST_ACT_LO || st == ST_ACT_HI) {
+          sc.status[r] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
           sc.halt[r] = 1;
         }
       }
@@ -316,136 +377,166 @@ __global__ void __launch_bounds__(256) k_half_stop(BicgScal sc, int32_t ngroups,
   }
 }
 
-__global__ void k_mark_halted(BicgScal sc, int32_t nruns) {
-  for (int run = threadIdx.x; run < nruns; run += blockDim.x)
-    if (sc.halt[run] && sc.status[run] != RUN_DONE) sc.status[run] = RUN_HALTED;
-}
-
 // ------------------------------------------------------------------ host driver
-static int32_t grid8(int64_t nlogical) { return (int32_t)((nlogical + 7) / 8 * 8); }
-
 template <typename T>
-int32_t bicg_alloc(BicgBatch<T>& b) {
-  cbs_system* s = b.sys;
+static int32_t alloc_vecs(cbs_system* s, BicgVecs<T>& v, size_t nruns, const std::string& pre) {
   Workspace& ws = s->ws;
-  const size_t nv = (size_t)b.nruns * s->N;
-  const bool f32 = std::is_same<T, float>::value;
-  const char* pre = f32 ? "b32." : "b64.";
-  std::string k = pre;
-  CBS_TRY(ws_get(ws, (k + "R").c_str(), nv, &b.R));
-  CBS_TRY(ws_get(ws, (k + "P0").c_str(), nv, &b.Pb[0]));
-  CBS_TRY(ws_get(ws, (k + "P1").c_str(), nv, &b.Pb[1]));
-  CBS_TRY(ws_get(ws, (k + "Q").c_str(), nv, &b.Q));
-  CBS_TRY(ws_get(ws, (k + "X").c_str(), nv, &b.X));
-  CBS_TRY(ws_get(ws, "bicg.Y", nv, &b.Y));
-  const int na = s->proj.n_atoms;
-  if (na > 0) CBS_TRY(ws_get(ws, (k + "KT").c_str(), (size_t)b.nruns * na * 12, &b.KT));
-  if (f32) {
-    CBS_TRY(ws_get(ws, "b32.Q64", nv, &b.Q64));
-    if (na > 0) CBS_TRY(ws_get(ws, "b32.KT64", (size_t)b.nruns * na * 12, &b.KT64));
-  } else {
-    b.Q64 = reinterpret_cast<Pair<double>*>(b.Q);
-    b.KT64 = reinterpret_cast<Pair<double>*>(b.KT);
-  }
-  b.tile_y = s->tile_y[f32 ? 1 : 0];
-  b.ntiles = stencil_tiles(s, b.tile_y);
-  b.nchunks = update_chunks(s);
-  CBS_TRY(ws_get(ws, "bicg.sig", (size_t)b.nruns * b.ntiles, &b.sig_part));
-  CBS_TRY(ws_get(ws, "bicg.signl", (size_t)b.nruns * std::max(na, 1), &b.signl));
-  CBS_TRY(ws_get(ws, "bicg.upd", (size_t)b.nruns * b.nchunks * 4, &b.upd_part));
-  CBS_TRY(ws_get(ws, "bicg.ru", (size_t)b.nruns * b.nchunks * 4, &b.ru_part));
-  const size_t R = b.nruns;
-  CBS_TRY(ws_get(ws, "sc.alpha", R, &b.sc.alpha));
-  CBS_TRY(ws_get(ws, "sc.xcoef", R, &b.sc.xcoef));
-  CBS_TRY(ws_get(ws, "sc.beta", R, &b.sc.beta));
-  CBS_TRY(ws_get(ws, "sc.rho", R, &b.sc.rho));
-  CBS_TRY(ws_get(ws, "sc.rhop", R, &b.sc.rho_prev));
-  CBS_TRY(ws_get(ws, "sc.vn2", R, &b.sc.vn2));
-  CBS_TRY(ws_get(ws, "sc.relres", 2 * R, &b.sc.relres));
-  CBS_TRY(ws_get(ws, "sc.ruthr", R, &b.sc.ru_thr));
-  CBS_TRY(ws_get(ws, "sc.status", R, &b.sc.status));
-  CBS_TRY(ws_get(ws, "sc.iters", R, &b.sc.iters));
-  CBS_TRY(ws_get(ws, "sc.brk", R, &b.sc.brk));
-  CBS_TRY(ws_get(ws, "sc.halt", R, &b.sc.halt));
-  CBS_TRY(ws_get(ws, "sc.nru", R, &b.sc.nru));
-  CBS_TRY(ws_get(ws, "sc.nact", 1, &b.sc.n_active));
+  const size_t nv = nruns * s->N;
+  CBS_TRY(ws_get(ws, (pre + "R").c_str(), nv, &v.R));
+  CBS_TRY(ws_get(ws, (pre + "P0").c_str(), nv, &v.Pb[0]));
+  CBS_TRY(ws_get(ws, (pre + "P1").c_str(), nv, &v.Pb[1]));
+  CBS_TRY(ws_get(ws, (pre + "Q").c_str(), nv, &v.Q));
+  CBS_TRY(ws_get(ws, (pre + "X").c_str(), nv, &v.X));
+  if (s->proj.n_atoms > 0) CBS_TRY(ws_get(ws, (pre + "KT").c_str(), nruns * s->proj.n_atoms * 12, &v.KT));
+  v.tile_y = s->tile_y[std::is_same<T, float>::value ? 1 : 0];
+  v.ntiles = stencil_tiles(s, v.tile_y);
+  CBS_TRY(ws_get(ws, (pre + "sig").c_str(), nruns * v.ntiles, &v.sig));
   return CBS_OK;
 }
 
-template <typename T>
-int32_t bicg_enqueue_init(BicgBatch<T>& b, hipStream_t st) {
+int32_t bicg_alloc(BicgSolve& b, const char* tag) {
+  cbs_system* s = b.sys;
+  Workspace& ws = s->ws;
+  const std::string t = tag;
+  const size_t R = b.nruns;
+  CBS_TRY(autotune_tiles(s, nullptr));
+  if (b.mixed) CBS_TRY(alloc_vecs<float>(s, b.lo, R, t + ".lo."));
+  CBS_TRY(alloc_vecs<double>(s, b.hi, R, t + ".hi."));
+  CBS_TRY(ws_get(ws, (t + ".Y").c_str(), R * s->N, &b.Y));
+  b.nchunks = update_chunks(s);
+  const int na = s->proj.n_atoms;
+  CBS_TRY(ws_get(ws, (t + ".signl").c_str(), R * std::max(na, 1), &b.signl));
+  CBS_TRY(ws_get(ws, (t + ".upd").c_str(), R * b.nchunks * 4, &b.upd_part));
+  CBS_TRY(ws_get(ws, (t + ".ru").c_str(), R * b.nchunks * 4, &b.ru_part));
+  CBS_TRY(ws_get(ws, (t + ".alpha").c_str(), R, &b.sc.alpha));
+  CBS_TRY(ws_get(ws, (t + ".xcoef").c_str(), R, &b.sc.xcoef));
+  CBS_TRY(ws_get(ws, (t + ".beta").c_str(), R, &b.sc.beta));
+  CBS_TRY(ws_get(ws, (t + ".rho").c_str(), R, &b.sc.rho));
+  CBS_TRY(ws_get(ws, (t + ".rhop").c_str(), R, &b.sc.rho_prev));
+  CBS_TRY(ws_get(ws, (t + ".vn2").c_str(), R, &b.sc.vn2));
+  CBS_TRY(ws_get(ws, (t + ".relres").c_str(), 2 * R, &b.sc.relres));
+  CBS_TRY(ws_get(ws, (t + ".ruthr").c_str(), R, &b.sc.ru_thr));
+  CBS_TRY(ws_get(ws, (t + ".status").c_str(), R, &b.sc.status));
+  CBS_TRY(ws_get(ws, (t + ".iters").c_str(), R, &b.sc.iters));
+  CBS_TRY(ws_get(ws, (t + ".brk").c_str(), R, &b.sc.brk));
+  CBS_TRY(ws_get(ws, (t + ".halt").c_str(), R, &b.sc.halt));
+  CBS_TRY(ws_get(ws, (t + ".nru").c_str(), R, &b.sc.nru));
+  CBS_TRY(ws_get(ws, (t + ".conv").c_str(), R, &b.sc.conv));
+  CBS_TRY(ws_get(ws, (t + ".nact").c_str(), 2, &b.sc.n_active));
+  return CBS_OK;
+}
+
+static int32_t enqueue_init(BicgSolve& b, hipStream_t st) {
   cbs_system* s = b.sys;
   const int64_t total = (int64_t)b.nruns * s->N;
   const int g = (int)std::min<int64_t>((total + 255) / 256, 1 << 20);
-  hipLaunchKernelGGL(k_bicg_init<T>, dim3(g), dim3(256), 0, st, s->N, b.nruns, b.L, b.V, b.R, b.Pb[0],
-                     b.Pb[1], b.X, b.Y);
+  hipLaunchKernelGGL(k_bicg_init<double>, dim3(g), dim3(256), 0, st, s->N, b.nruns, b.L, b.V, b.Vd ? b.Vd : b.V, b.hi.R, b.hi.Pb[0],
+                     b.hi.Pb[1], b.hi.X, b.Y);
   CBS_HIP(hipGetLastError());
+  if (b.mixed) {
+    hipLaunchKernelGGL(k_bicg_init<float>, dim3(g), dim3(256), 0, st, s->N, b.nruns, b.L, b.V, b.Vd ? b.Vd : b.V, b.lo.R, b.lo.Pb[0],
+                       b.lo.Pb[1], b.lo.X, (Pair<double>*)nullptr);
+    CBS_HIP(hipGetLastError());
+  }
   const int nl = b.nruns * b.nchunks;
-  hipLaunchKernelGGL(k_partials<T>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl,
-                     (const Pair<T>*)b.R, b.upd_part);
+  if (b.mixed)
+    hipLaunchKernelGGL(k_partials<float>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl,
+                       (const Pair<float>*)b.lo.R, b.upd_part);
+  else
+    hipLaunchKernelGGL(k_partials<double>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl,
+                       (const Pair<double>*)b.hi.R, b.upd_part);
   CBS_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_s0, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.upd_part,
-                     b.ru_factor);
+                     (int32_t)(b.mixed ? ST_ACT_LO : ST_ACT_HI), b.ru_factor);
   CBS_HIP(hipGetLastError());
   return CBS_OK;
 }
 
 template <typename T>
-int32_t bicg_enqueue_iter(BicgBatch<T>& b, int parity, hipStream_t st) {
+static int32_t enqueue_stencil_bra(BicgSolve& b, BicgVecs<T>& v, int32_t need, int parity, hipStream_t st) {
   cbs_system* s = b.sys;
-  Pair<T>* pnew = b.Pb[parity & 1];
-  Pair<T>* pold = b.Pb[(parity + 1) & 1];
   StencilLaunch l{};
   l.nruns = b.nruns;
-  l.rin = b.R;
-  l.pold = pold;
-  l.pnew = pnew;
-  l.q = b.Q;
-  l.x = b.X;
+  l.rin = v.R;
+  l.pold = v.Pb[(parity + 1) & 1];
+  l.pnew = v.Pb[parity & 1];
+  l.q = v.Q;
+  l.x = v.X;
   l.coef = b.coef;
   l.beta = b.sc.beta;
   l.xcoef = b.sc.xcoef;
   l.status = b.sc.status;
-  l.need_status = RUN_ACTIVE;
-  l.sig_part = b.sig_part;
-  if (b.pev0) CBS_HIP(hipEventRecord(b.pev0, st));
-  CBS_TRY(launch_stencil<T>(s, true, l, b.tile_y, st));
-  if (b.pev1) CBS_HIP(hipEventRecord(b.pev1, st));
+  l.need_status = need;
+  l.sig_part = v.sig;
+  if (v.ev0) CBS_HIP(hipEventRecord(v.ev0, st));
+  CBS_TRY(launch_stencil<T>(s, true, l, v.tile_y, st));
+  if (v.ev1) CBS_HIP(hipEventRecord(v.ev1, st));
+  if (s->proj.n_atoms > 0)
+    CBS_TRY(launch_bra<T>(s, b.nruns, v.Pb[parity & 1], b.coef, b.sc.status, need, v.KT, b.signl, st, true));
+  return CBS_OK;
+}
+
+static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
+  cbs_system* s = b.sys;
   const int na = s->proj.n_atoms;
-  if (na > 0) CBS_TRY(launch_bra<T>(s, b.nruns, pnew, b.coef, b.sc.status, RUN_ACTIVE, b.KT, b.signl, st));
-  hipLaunchKernelGGL(k_s1, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.ntiles, na,
-                     (const double2*)b.sig_part, (const double2*)b.signl);
+  const int nl = b.nruns * b.nchunks;
+  if (b.mixed) CBS_TRY(enqueue_stencil_bra<float>(b, b.lo, ST_ACT_LO, parity, st));
+  CBS_TRY(enqueue_stencil_bra<double>(b, b.hi, ST_ACT_HI, parity, st));
+  hipLaunchKernelGGL(k_s1, dim3(1), dim3(256), 0, st, b.sc, b.nruns, na, (const double2*)b.lo.sig, b.lo.ntiles,
+                     (const double2*)b.hi.sig, b.hi.ntiles, (const double2*)b.signl);
   CBS_HIP(hipGetLastError());
-  CBS_TRY(launch_update<T>(s, b.nruns, b.R, b.Q, b.KT, b.sc.alpha, b.sc.status, b.upd_part, b.nchunks, st));
-  hipLaunchKernelGGL(k_s2, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.upd_part,
-                     b.tol, b.max_iter);
+  if (b.mixed)
+    CBS_TRY(launch_update<float>(s, b.nruns, b.lo.R, b.lo.Q, b.lo.KT, b.sc.alpha, b.sc.status, ST_ACT_LO,
+                                 b.upd_part, b.nchunks, st));
+  CBS_TRY(launch_update<double>(s, b.nruns, b.hi.R, b.hi.Q, b.hi.KT, b.sc.alpha, b.sc.status, ST_ACT_HI,
+                                b.upd_part, b.nchunks, st));
+  hipLaunchKernelGGL(k_s2, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.upd_part, b.tol,
+                     b.max_iter);
   CBS_HIP(hipGetLastError());
   if (b.half_stop && b.n_q > 0) {
     hipLaunchKernelGGL(k_half_stop, dim3(1), dim3(256), 0, st, b.sc, b.nruns / (b.n_q * b.L), b.n_q, b.L);
     CBS_HIP(hipGetLastError());
   }
-  // reliable update of the marked runs
-  const int nl = b.nruns * b.nchunks;
-  hipLaunchKernelGGL(k_ru_pre<T>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl,
-                     (const int32_t*)b.sc.status, (const double2*)b.sc.xcoef, (const Pair<T>*)pnew, b.X, b.Y);
+  // residual replacement of the marked runs
+  if (b.mixed)
+    hipLaunchKernelGGL(k_ru_pre<float>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl,
+                       (const int32_t*)b.sc.status, (int32_t)ST_RU_LO, (const double2*)b.sc.xcoef,
+                       (const Pair<float>*)b.lo.Pb[parity & 1], b.lo.X, b.Y);
+  hipLaunchKernelGGL(k_ru_pre<double>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl,
+                     (const int32_t*)b.sc.status, (int32_t)ST_RU_HI, (const double2*)b.sc.xcoef,
+                     (const Pair<double>*)b.hi.Pb[parity & 1], b.hi.X, b.Y);
   CBS_HIP(hipGetLastError());
-  StencilLaunch r{};
-  r.nruns = b.nruns;
-  r.rin = b.Y;
-  r.q = b.Q64;
-  r.coef = b.coef;
-  r.status = b.sc.status;
-  r.need_status = RUN_RU;
-  CBS_TRY(launch_stencil<double>(s, false, r, s->tile_y[0], st));
-  if (na > 0) CBS_TRY(launch_bra<double>(s, b.nruns, b.Y, b.coef, b.sc.status, RUN_RU, b.KT64, nullptr, st));
-  hipLaunchKernelGGL(k_ru_post<T>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, b.L, na,
-                     (const int32_t*)b.sc.status, b.V, (const Pair<double>*)b.Q64,
-                     (const Pair<double>*)b.KT64, s->proj.pt_off, s->proj.pt_key,
-                     (const double*)s->proj.pt_u64, b.R, b.ru_part);
+  for (int ph = b.mixed ? 0 : 1; ph < 2; ++ph) {
+    const int32_t need = ph ? ST_RU_HI : ST_RU_LO;
+    StencilLaunch r{};
+    r.nruns = b.nruns;
+    r.rin = b.Y;
+    r.q = b.hi.Q;
+    r.coef = b.coef;
+    r.status = b.sc.status;
+    r.need_status = need;
+    CBS_TRY(launch_stencil<double>(s, false, r, b.hi.tile_y, st));
+    if (na > 0) CBS_TRY(launch_bra<double>(s, b.nruns, b.Y, b.coef, b.sc.status, need, b.hi.KT, nullptr, st, true));
+  }
+  if (b.mixed)
+    hipLaunchKernelGGL(k_ru_post<float>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, b.L, na,
+                       (const int32_t*)b.sc.status, (int32_t)ST_RU_LO, b.V, b.Vd ? b.Vd : b.V, (const Pair<double>*)b.hi.Q,
+                       (const Pair<double>*)b.hi.KT, s->proj.pt_off, s->proj.pt_key, (const double*)s->proj.pt_u64,
+                       b.lo.R, b.hi.R, b.ru_part);
+  hipLaunchKernelGGL(k_ru_post<double>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, b.L, na,
+                     (const int32_t*)b.sc.status, (int32_t)ST_RU_HI, b.V, b.Vd ? b.Vd : b.V, (const Pair<double>*)b.hi.Q,
+                     (const Pair<double>*)b.hi.KT, s->proj.pt_off, s->proj.pt_key, (const double*)s->proj.pt_u64,
+                     b.hi.R, (Pair<double>*)nullptr, b.ru_part);
   CBS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_s3, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.ru_part,
-                     b.tol, b.max_iter, b.max_ru, b.ru_factor);
+  hipLaunchKernelGGL(k_s3, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.ru_part, b.tol,
+                     b.max_iter, b.max_ru, b.ru_factor, b.switch_tol);
   CBS_HIP(hipGetLastError());
+  if (b.mixed) {
+    hipLaunchKernelGGL(k_widen, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, (const int32_t*)b.sc.conv,
+                       (const Pair<float>*)b.lo.Pb[parity & 1], b.hi.Pb[parity & 1]);
+    hipLaunchKernelGGL(k_clear_conv, dim3(1), dim3(256), 0, st, b.sc, b.nruns);
+    CBS_HIP(hipGetLastError());
+  }
   return CBS_OK;
 }
 
@@ -454,142 +545,145 @@ static bool use_graphs() {
   return !(e && e[0] == '1');
 }
 
-// Runs the whole iteration on an internal stream ordered after `user` and before
-// its return point.  Several batches (systems) advance in the same graph.
-// Profile mode: iterations are launched one by one (no graph); every stencil launch of
-// every batch is bracketed by events on the stream it runs on, and the active-run count
-// is read back after each iteration to account the launch's algorithmic bytes.
-template <typename T>
-static int32_t bicg_run_profiled(std::vector<BicgBatch<T>*>& batches, hipStream_t st, int32_t max_iter) {
-  std::vector<int32_t> active(batches.size());
-  for (size_t i = 0; i < batches.size(); ++i) {
-    active[i] = batches[i]->nruns;
-    CBS_HIP(hipEventCreate(&batches[i]->pev0));
-    CBS_HIP(hipEventCreate(&batches[i]->pev1));
+// Profile mode: iterations launched one by one; each stencil launch is bracketed by
+// events on the stream it runs on and the active-run counts are read back after every
+// iteration to account each launch's algorithmic bytes.
+static int32_t run_profiled(std::vector<BicgSolve*>& solves, hipStream_t st, int32_t max_iter) {
+  std::vector<int32_t> act(2 * solves.size());
+  for (size_t i = 0; i < solves.size(); ++i) {
+    BicgSolve& b = *solves[i];
+    act[2 * i] = b.mixed ? b.nruns : 0;
+    act[2 * i + 1] = b.mixed ? 0 : b.nruns;
+    CBS_HIP(hipEventCreate(&b.hi.ev0));
+    CBS_HIP(hipEventCreate(&b.hi.ev1));
+    if (b.mixed) {
+      CBS_HIP(hipEventCreate(&b.lo.ev0));
+      CBS_HIP(hipEventCreate(&b.lo.ev1));
+    }
   }
   int32_t rc = CBS_OK;
+  int32_t hna[2];
   for (int it = 0; it <= max_iter + 1 && rc == CBS_OK; ++it) {
     int any = 0;
-    for (size_t i = 0; i < batches.size() && rc == CBS_OK; ++i) {
-      BicgBatch<T>& b = *batches[i];
-      if (active[i] == 0) continue;
-      rc = bicg_enqueue_iter<T>(b, it, st);
+    for (size_t i = 0; i < solves.size() && rc == CBS_OK; ++i) {
+      BicgSolve& b = *solves[i];
+      if (act[2 * i] + act[2 * i + 1] == 0) continue;
+      rc = enqueue_iter(b, it, st);
       if (rc != CBS_OK) break;
-      int32_t na = 0;
-      CBS_HIP(hipMemcpyAsync(&na, b.sc.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      CBS_HIP(hipMemcpyAsync(hna, b.sc.n_active, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
       CBS_HIP(hipStreamSynchronize(st));
+      const double passes = (it == 0) ? 4.0 : 6.0;   // r, p_old (+ x) in; p_new, q (+ x) out
       float ms = 0;
-      CBS_HIP(hipEventElapsedTime(&ms, b.pev0, b.pev1));
-      const double passes = (it == 0) ? 4.0 : 6.0;
-      b.prof_ms += ms;
-      b.prof_launches += 1;
-      b.prof_bytes += (double)active[i] * passes * b.sys->N * sizeof(Pair<T>) + (double)b.sys->N * sizeof(T);
-      active[i] = na;
-      any += na;
+      if (b.mixed && act[2 * i] > 0) {
+        CBS_HIP(hipEventElapsedTime(&ms, b.lo.ev0, b.lo.ev1));
+        b.lo.prof_ms += ms;
+        b.lo.prof_launches += 1;
+        b.lo.prof_bytes += (double)act[2 * i] * passes * b.sys->N * sizeof(Pair<float>) + b.sys->N * sizeof(float);
+      }
+      if (act[2 * i + 1] > 0) {
+        CBS_HIP(hipEventElapsedTime(&ms, b.hi.ev0, b.hi.ev1));
+        b.hi.prof_ms += ms;
+        b.hi.prof_launches += 1;
+        b.hi.prof_bytes += (double)act[2 * i + 1] * passes * b.sys->N * sizeof(Pair<double>) + b.sys->N * sizeof(double);
+      }
+      act[2 * i] = hna[0];
+      act[2 * i + 1] = hna[1];
+      any += hna[0] + hna[1];
     }
     if (any == 0) break;
   }
-  for (auto* b : batches) {
-    (void)hipEventDestroy(b->pev0);
-    (void)hipEventDestroy(b->pev1);
-    b->pev0 = b->pev1 = nullptr;
+  for (auto* b : solves) {
+    hipEvent_t evs[4] = {b->hi.ev0, b->hi.ev1, b->lo.ev0, b->lo.ev1};
+    for (auto e : evs)
+      if (e) (void)hipEventDestroy(e);
+    b->hi.ev0 = b->hi.ev1 = b->lo.ev0 = b->lo.ev1 = nullptr;
   }
   return rc;
 }
 
-template <typename T>
-int32_t bicg_run(std::vector<BicgBatch<T>*>& batches, hipStream_t user, int32_t chunk, int32_t max_iter,
+// Runs all solves to completion on an internal stream ordered after `user` (and `user`
+// waits for it at the end).  Several solves (systems) advance in the same graph.
+int32_t bicg_run(std::vector<BicgSolve*>& solves, hipStream_t user, int32_t chunk, int32_t max_iter,
                  double* elapsed_ms, bool profile) {
-  if (batches.empty()) return CBS_OK;
+  if (solves.empty()) return CBS_OK;
   if (chunk < 2) chunk = 2;
   if (chunk % 2) chunk += 1;
   hipStream_t st = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  CBS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  int32_t* hact = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
   struct Guard {
     hipStream_t& s;
     hipEvent_t& a;
     hipEvent_t& b;
+    int32_t*& h;
+    hipGraphExec_t& x;
+    hipGraph_t& g;
     ~Guard() {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+      if (h) (void)hipHostFree(h);
       if (a) (void)hipEventDestroy(a);
       if (b) (void)hipEventDestroy(b);
       if (s) (void)hipStreamDestroy(s);
     }
-  } guard{st, ev0, ev1};
+  } guard{st, ev0, ev1, hact, exec, graph};
+  CBS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   CBS_HIP(hipEventCreate(&ev0));
   CBS_HIP(hipEventCreate(&ev1));
   CBS_HIP(hipEventRecord(ev0, user));
   CBS_HIP(hipStreamWaitEvent(st, ev0, 0));
-  for (auto* b : batches) CBS_TRY(bicg_enqueue_init<T>(*b, st));
-  int32_t* hact = nullptr;
-  CBS_HIP(hipHostMalloc(&hact, sizeof(int32_t) * batches.size(), hipHostMallocDefault));
-  struct HGuard {
-    int32_t* p;
-    ~HGuard() {
-      if (p) (void)hipHostFree(p);
-    }
-  } hg{hact};
-
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
+  for (auto* b : solves) CBS_TRY(enqueue_init(*b, st));
+  CBS_HIP(hipHostMalloc(&hact, sizeof(int32_t) * 2 * solves.size(), hipHostMallocDefault));
   const bool graphs = use_graphs() && !profile;
   if (graphs) {
     CBS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
     int32_t rc = CBS_OK;
     for (int k = 0; k < chunk && rc == CBS_OK; ++k)
-      for (auto* b : batches)
-        if (rc == CBS_OK) rc = bicg_enqueue_iter<T>(*b, k, st);
+      for (auto* b : solves)
+        if (rc == CBS_OK) rc = enqueue_iter(*b, k, st);
     hipError_t e = hipStreamEndCapture(st, &graph);
-    if (rc != CBS_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return rc;
-    }
+    if (rc != CBS_OK) return rc;
     CBS_HIP(e);
     CBS_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   }
   auto t0 = std::chrono::steady_clock::now();
   int32_t rc = CBS_OK;
-  const int max_chunks = profile ? 0 : (max_iter + 2) / chunk + 2;
-  if (profile) rc = bicg_run_profiled<T>(batches, st, max_iter);
-  for (int c = 0; c < max_chunks; ++c) {
-    if (graphs) {
-      if (hipGraphLaunch(exec, st) != hipSuccess) {
-        set_error("hipGraphLaunch failed");
+  if (profile) {
+    rc = run_profiled(solves, st, max_iter);
+  } else {
+    const int max_chunks = (max_iter + 2) / chunk + 2;
+    for (int c = 0; c < max_chunks && rc == CBS_OK; ++c) {
+      if (graphs) {
+        if (hipGraphLaunch(exec, st) != hipSuccess) {
+          set_error("hipGraphLaunch failed");
+          rc = CBS_EHIP;
+          break;
+        }
+      } else {
+        for (int k = 0; k < chunk && rc == CBS_OK; ++k)
+          for (auto* b : solves)
+            if (rc == CBS_OK) rc = enqueue_iter(*b, k, st);
+        if (rc != CBS_OK) break;
+      }
+      for (size_t i = 0; i < solves.size(); ++i)
+        if (hipMemcpyAsync(hact + 2 * i, solves[i]->sc.n_active, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+            hipSuccess) {
+          set_error("copy of the active-run count failed");
+          rc = CBS_EHIP;
+        }
+      if (rc != CBS_OK) break;
+      if (hipStreamSynchronize(st) != hipSuccess) {
+        set_error("BiCG iteration failed: %s", hipGetErrorString(hipGetLastError()));
         rc = CBS_EHIP;
         break;
       }
-    } else {
-      for (int k = 0; k < chunk && rc == CBS_OK; ++k)
-        for (auto* b : batches)
-          if (rc == CBS_OK) rc = bicg_enqueue_iter<T>(*b, k, st);
-      if (rc != CBS_OK) break;
-    }
-    for (size_t i = 0; i < batches.size(); ++i)
-      if (hipMemcpyAsync(hact + i, batches[i]->sc.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
-          hipSuccess) {
-        rc = CBS_EHIP;
-        set_error("copy of the active-run count failed");
-      }
-    if (rc != CBS_OK) break;
-    if (hipStreamSynchronize(st) != hipSuccess) {
-      set_error("BiCG iteration failed: %s", hipGetErrorString(hipGetLastError()));
-      rc = CBS_EHIP;
-      break;
-    }
-    int any = 0;
-    for (size_t i = 0; i < batches.size(); ++i) any += hact[i];
-    if (any == 0) break;
-  }
-  if (rc == CBS_OK) {
-    for (auto* b : batches) {
-      if (b->half_stop) {
-        hipLaunchKernelGGL(k_mark_halted, dim3(1), dim3(256), 0, st, b->sc, b->nruns);
-        CBS_HIP(hipGetLastError());
-      }
+      int any = 0;
+      for (size_t i = 0; i < 2 * solves.size(); ++i) any += hact[i];
+      if (any == 0) break;
     }
   }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
   CBS_HIP(hipStreamSynchronize(st));
   auto t1 = std::chrono::steady_clock::now();
   if (elapsed_ms) *elapsed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -598,28 +692,32 @@ int32_t bicg_run(std::vector<BicgBatch<T>*>& batches, hipStream_t user, int32_t 
   return rc;
 }
 
-// Summaries copied to the host after a run.
-template <typename T>
-int32_t bicg_collect(BicgBatch<T>& b, std::vector<int32_t>& iters, std::vector<double>& relres,
-                     std::vector<int32_t>& status, hipStream_t st) {
-  iters.resize(b.nruns);
-  relres.resize(2 * (size_t)b.nruns);
-  status.resize(b.nruns);
-  CBS_HIP(hipMemcpyAsync(iters.data(), b.sc.iters, b.nruns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  CBS_HIP(hipMemcpyAsync(relres.data(), b.sc.relres, 2 * b.nruns * sizeof(double), hipMemcpyDeviceToHost, st));
-  CBS_HIP(hipMemcpyAsync(status.data(), b.sc.status, b.nruns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+int32_t bicg_collect(BicgSolve& b, NodeSolve& out, hipStream_t st) {
+  out.nruns = b.nruns;
+  out.iters.resize(b.nruns);
+  out.relres.resize(2 * (size_t)b.nruns);
+  out.status.resize(b.nruns);
+  std::vector<int32_t> nru(b.nruns);
+  CBS_HIP(hipMemcpyAsync(out.iters.data(), b.sc.iters, b.nruns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CBS_HIP(hipMemcpyAsync(out.relres.data(), b.sc.relres, 2 * b.nruns * sizeof(double), hipMemcpyDeviceToHost, st));
+  CBS_HIP(hipMemcpyAsync(out.status.data(), b.sc.status, b.nruns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CBS_HIP(hipMemcpyAsync(nru.data(), b.sc.nru, b.nruns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   CBS_HIP(hipStreamSynchronize(st));
+  out.n_ru = 0;
+  for (int v : nru) out.n_ru = std::max(out.n_ru, v);
+  out.Y = b.Y;
+  // the stencil of the phase that did most of the work
+  if (b.mixed) {
+    out.prof_launches = b.lo.prof_launches;
+    out.prof_ms = b.lo.prof_ms;
+    out.prof_bytes = b.lo.prof_bytes;
+  } else {
+    out.prof_launches = b.hi.prof_launches;
+    out.prof_ms = b.hi.prof_ms;
+    out.prof_bytes = b.hi.prof_bytes;
+  }
   return CBS_OK;
 }
-
-template int32_t bicg_alloc<double>(BicgBatch<double>&);
-template int32_t bicg_alloc<float>(BicgBatch<float>&);
-template int32_t bicg_run<double>(std::vector<BicgBatch<double>*>&, hipStream_t, int32_t, int32_t, double*, bool);
-template int32_t bicg_run<float>(std::vector<BicgBatch<float>*>&, hipStream_t, int32_t, int32_t, double*, bool);
-template int32_t bicg_collect<double>(BicgBatch<double>&, std::vector<int32_t>&, std::vector<double>&,
-                                      std::vector<int32_t>&, hipStream_t);
-template int32_t bicg_collect<float>(BicgBatch<float>&, std::vector<int32_t>&, std::vector<double>&,
-                                     std::vector<int32_t>&, hipStream_t);
 
 // ------------------------------------------------------------------ node coefficients
 void node_coefs(const double2* z, int32_t n_z, int32_t L, double E, std::vector<RunCoef>& out) {
@@ -641,8 +739,7 @@ void node_coefs(const double2* z, int32_t n_z, int32_t L, double E, std::vector<
 
 __global__ void k_split_pairs(int64_t N, int32_t nruns, const Pair<double>* Y, double2* ya, double2* yb) {
   const int64_t total = N * nruns;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
     const Pair<double> v = Y[g];
     ya[g] = v.a;
     yb[g] = v.b;
@@ -658,7 +755,17 @@ int32_t split_pairs(int64_t N, int32_t nruns, const Pair<double>* Y, double2* ya
   return CBS_OK;
 }
 
-// Complete step-1 solve of one system at one energy, shared by cbs_bicg and cbs_solve.
+void configure_solve(BicgSolve& b, const cbs_params* prm) {
+  b.mixed = prm->precision == CBS_MIXED;
+  b.tol = prm->tol;
+  b.ru_factor = 0.1;
+  b.switch_tol = b.mixed ? std::max(prm->inner_tol, prm->tol) : 0.0;
+  b.max_iter = prm->max_iter;
+  b.max_ru = b.mixed ? std::max(prm->max_refine, 1) : (1 << 30);
+  b.half_stop = prm->half_stop;
+}
+
+// Step-1 solve of one system at one energy, shared by cbs_bicg and cbs_solve.
 int32_t solve_nodes(cbs_system* s, double E, const double2* z, int32_t n_z, int32_t L, const double2* V,
                     const cbs_params* prm, hipStream_t st, NodeSolve& out) {
   std::vector<RunCoef> hc;
@@ -667,55 +774,20 @@ int32_t solve_nodes(cbs_system* s, double E, const double2* z, int32_t n_z, int3
   const int32_t nruns = n_z * L;
   CBS_TRY(ws_get(s->ws, "bicg.coef", (size_t)nruns, &coef));
   CBS_HIP(hipMemcpyAsync(coef, hc.data(), nruns * sizeof(RunCoef), hipMemcpyHostToDevice, st));
-  const bool mixed = prm->precision == CBS_MIXED;
-  const int32_t max_ru = mixed ? std::max(prm->max_refine, 1) : 1 << 30;
-  int32_t rc = CBS_OK;
-  if (mixed) {
-    BicgBatch<float> b{};
-    b.sys = s;
-    b.nruns = nruns;
-    b.L = L;
-    b.n_q = n_z;
-    b.V = V;
-    b.coef = coef;
-    b.tol = prm->tol;
-    b.ru_factor = prm->inner_tol;
-    b.max_iter = prm->max_iter;
-    b.max_ru = max_ru;
-    b.half_stop = prm->half_stop;
-    CBS_TRY(bicg_alloc<float>(b));
-    std::vector<BicgBatch<float>*> v{&b};
-    rc = bicg_run<float>(v, st, prm->chunk, prm->max_iter, &out.ms, prm->profile != 0);
-    if (rc != CBS_OK) return rc;
-    CBS_TRY(bicg_collect<float>(b, out.iters, out.relres, out.status, st));
-    out.Y = b.Y;
-    out.prof_launches = b.prof_launches;
-    out.prof_ms = b.prof_ms;
-    out.prof_bytes = b.prof_bytes;
-  } else {
-    BicgBatch<double> b{};
-    b.sys = s;
-    b.nruns = nruns;
-    b.L = L;
-    b.n_q = n_z;
-    b.V = V;
-    b.coef = coef;
-    b.tol = prm->tol;
-    b.ru_factor = 0.0;
-    b.max_iter = prm->max_iter;
-    b.max_ru = max_ru;
-    b.half_stop = prm->half_stop;
-    CBS_TRY(bicg_alloc<double>(b));
-    std::vector<BicgBatch<double>*> v{&b};
-    rc = bicg_run<double>(v, st, prm->chunk, prm->max_iter, &out.ms, prm->profile != 0);
-    if (rc != CBS_OK) return rc;
-    CBS_TRY(bicg_collect<double>(b, out.iters, out.relres, out.status, st));
-    out.Y = b.Y;
-    out.prof_launches = b.prof_launches;
-    out.prof_ms = b.prof_ms;
-    out.prof_bytes = b.prof_bytes;
-  }
-  out.nruns = nruns;
+  BicgSolve b;
+  b.sys = s;
+  b.nruns = nruns;
+  b.L = L;
+  b.n_q = n_z;
+  b.V = V;
+  b.coef = coef;
+  configure_solve(b, prm);
+  CBS_TRY(bicg_alloc(b, "bicg"));
+  std::vector<BicgSolve*> v{&b};
+  CBS_TRY(bicg_run(v, st, prm->chunk, prm->max_iter, &out.ms, prm->profile != 0));
+  CBS_TRY(bicg_collect(b, out, st));
+  // the host coefficient array must outlive the asynchronous copy
+  CBS_HIP(hipStreamSynchronize(st));
   return CBS_OK;
 }
 
@@ -724,8 +796,8 @@ int32_t check_params(const cbs_params* p, bool need_moments) {
     set_error("params is NULL");
     return CBS_EINVAL;
   }
-  if (!(p->lambda_min > 0 && p->lambda_min < 1) || p->n_q < 1 || p->n_rhs < 1 || !(p->tol > 0) ||
-      p->max_iter < 1 || (p->precision != CBS_FP64 && p->precision != CBS_MIXED) ||
+  if (!(p->lambda_min > 0 && p->lambda_min < 1) || p->n_q < 1 || p->n_rhs < 1 || !(p->tol > 0) || p->max_iter < 1 ||
+      (p->precision != CBS_FP64 && p->precision != CBS_MIXED) ||
       (p->precision == CBS_MIXED && !(p->inner_tol > 0 && p->inner_tol < 1))) {
     set_error("invalid solver parameters");
     return CBS_EINVAL;
@@ -744,9 +816,9 @@ int32_t check_params(const cbs_params* p, bool need_moments) {
 
 using namespace cbs;
 
-extern "C" int32_t cbs_bicg(cbs_system* s, double E, int32_t n_z, const double* z, int32_t n_rhs,
-                            const void* V, const cbs_params* prm, void* Y, void* Yt, int32_t* iters,
-                            double* relres, cbs_info* info, void* stream) {
+extern "C" int32_t cbs_bicg(cbs_system* s, double E, int32_t n_z, const double* z, int32_t n_rhs, const void* V,
+                            const cbs_params* prm, void* Y, void* Yt, int32_t* iters, double* relres, cbs_info* info,
+                            void* stream) {
   if (!s || n_z < 1 || !z || n_rhs < 1 || !V || !Y || !Yt) {
     set_error("cbs_bicg: bad argument");
     return CBS_EINVAL;
@@ -771,7 +843,7 @@ extern "C" int32_t cbs_bicg(cbs_system* s, double E, int32_t n_z, const double* 
       relres[2 * r] = ns.relres[2 * r];
       relres[2 * r + 1] = ns.relres[2 * r + 1];
     }
-    noconv = noconv || ns.status[r] != RUN_DONE;
+    noconv = noconv || ns.status[r] != ST_DONE;
   }
   if (info) {
     std::memset(info, 0, sizeof(*info));
@@ -785,6 +857,7 @@ extern "C" int32_t cbs_bicg(cbs_system* s, double E, int32_t n_z, const double* 
     info->iters_max = im;
     info->iters_mean = sum / ns.nruns;
     info->max_solve_resid = mx;
+    info->refine_steps = ns.n_ru;
     info->t_solve_ms = ns.ms;
     info->matvecs = (int64_t)(2 * sum);
     info->stencil_launches = ns.prof_launches;
@@ -792,7 +865,7 @@ extern "C" int32_t cbs_bicg(cbs_system* s, double E, int32_t n_z, const double* 
     info->stencil_bytes = ns.prof_bytes;
   }
   if (noconv) {
-    set_error("cbs_bicg: %s", "some runs missed the tolerance");
+    set_error("cbs_bicg: some runs missed the tolerance");
     return CBS_ENOCONV;
   }
   return CBS_OK;

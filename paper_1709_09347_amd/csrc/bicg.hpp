@@ -1,4 +1,4 @@
-// BiCG batch state shared by the step-1 driver and the solver.
+// BiCG state shared by the step-1 driver and the solver.
 #pragma once
 
 #include <vector>
@@ -6,6 +6,20 @@
 #include "cbs_internal.hpp"
 
 namespace cbs {
+
+// Run states.  A run lives in the low-precision phase (complex64 recurrences) or the
+// high-precision phase (complex128); the state encodes the phase so every kernel
+// filters its runs with one comparison.
+enum BicgState : int32_t {
+  ST_ACT_LO = 0,   // iterating in complex64
+  ST_RU_LO = 1,    // complex64 run marked for a residual replacement this iteration
+  ST_DONE = 2,     // true complex128 residual below tol (primal and dual)
+  ST_NOCONV = 3,   // iteration or replacement cap reached
+  ST_BREAKDOWN = 4,
+  ST_HALTED = 5,   // stopped by the half-of-the-nodes rule
+  ST_ACT_HI = 6,   // iterating in complex128
+  ST_RU_HI = 7     // complex128 run marked for the final true-residual check
+};
 
 // Per-run scalars of the BiCG recurrences (device arrays, one entry per run).
 struct BicgScal {
@@ -16,40 +30,49 @@ struct BicgScal {
   double2* rho_prev;
   double* vn2;        // ||v||^2 of the run's right-hand side
   double* relres;     // [2*run]: primal, dual relative residual (last known)
-  double* ru_thr;     // next reliable update when the recursive residual falls below this
+  double* ru_thr;     // next replacement when the recursive residual falls below this
   int32_t* status;
   int32_t* iters;
   int32_t* brk;
   int32_t* halt;
   int32_t* nru;
-  int32_t* n_active;  // [1]
+  int32_t* conv;      // 1: switched to complex128 this iteration, search direction to convert
+  int32_t* n_active;  // [2]: active runs in the complex64 / complex128 phase
 };
 
+// Vectors of one precision (pairs: primal, dual per point, run-major).
 template <typename T>
-struct BicgBatch {
-  cbs_system* sys;
-  int32_t nruns, L, n_q, ntiles, nchunks, tile_y;
-  const double2* V;            // [L][N] right-hand sides
-  const RunCoef* coef;         // [nruns]
-  Pair<T>* R;
-  Pair<T>* Pb[2];
-  Pair<T>* Q;
-  Pair<T>* X;
-  Pair<T>* KT;
-  Pair<double>* Y;             // solutions (primal, dual), complex128
-  Pair<double>* Q64;
-  Pair<double>* KT64;
-  double2* sig_part;
-  double2* signl;
-  double* upd_part;
-  double* ru_part;
-  BicgScal sc;
-  double tol, ru_factor;
-  int32_t max_iter, max_ru, half_stop;
-  // profiling of the stencil launches (events recorded around each one when set)
-  hipEvent_t pev0 = nullptr, pev1 = nullptr;
+struct BicgVecs {
+  Pair<T>* R = nullptr;
+  Pair<T>* Pb[2] = {nullptr, nullptr};
+  Pair<T>* Q = nullptr;
+  Pair<T>* X = nullptr;
+  Pair<T>* KT = nullptr;
+  double2* sig = nullptr;   // [run][tile] stencil partials of sigma
+  int32_t tile_y = 0, ntiles = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;   // profiling of the stencil launches
   int64_t prof_launches = 0;
   double prof_ms = 0, prof_bytes = 0;
+};
+
+// One BiCG solve over a set of runs of one system (energies and nodes mixed freely:
+// every run carries its own coefficients and energy).
+struct BicgSolve {
+  cbs_system* sys = nullptr;
+  int32_t nruns = 0, L = 1, n_q = 0, nchunks = 0;
+  const double2* V = nullptr;       // [L][N]; run r uses right-hand side r % L
+  const double2* Vd = nullptr;      // dual right-hand sides (same indexing), NULL: V
+  const RunCoef* coef = nullptr;    // [nruns]
+  bool mixed = false;               // start in the complex64 phase
+  BicgVecs<float> lo;               // complex64 phase (mixed only)
+  BicgVecs<double> hi;              // complex128 phase (also the FP64 residual buffers)
+  Pair<double>* Y = nullptr;        // solutions (primal, dual), complex128
+  double2* signl = nullptr;
+  double* upd_part = nullptr;
+  double* ru_part = nullptr;
+  BicgScal sc{};
+  double tol = 1e-10, ru_factor = 0.1, switch_tol = 1e-4;
+  int32_t max_iter = 10000, max_ru = 1000, half_stop = 0;
 };
 
 struct NodeSolve {
@@ -60,19 +83,18 @@ struct NodeSolve {
   double ms = 0;
   int64_t prof_launches = 0;
   double prof_ms = 0, prof_bytes = 0;
+  int32_t n_ru = 0;
 };
 
-template <typename T> int32_t bicg_alloc(BicgBatch<T>& b);
-template <typename T>
-int32_t bicg_run(std::vector<BicgBatch<T>*>& batches, hipStream_t user, int32_t chunk, int32_t max_iter,
-                 double* elapsed_ms, bool profile = false);
-template <typename T>
-int32_t bicg_collect(BicgBatch<T>& b, std::vector<int32_t>& iters, std::vector<double>& relres,
-                     std::vector<int32_t>& status, hipStream_t st);
+int32_t bicg_alloc(BicgSolve& b, const char* tag);
+int32_t bicg_run(std::vector<BicgSolve*>& solves, hipStream_t user, int32_t chunk, int32_t max_iter,
+                 double* elapsed_ms, bool profile);
+int32_t bicg_collect(BicgSolve& b, NodeSolve& out, hipStream_t st);
 void node_coefs(const double2* z, int32_t n_z, int32_t L, double E, std::vector<RunCoef>& out);
 int32_t solve_nodes(cbs_system* s, double E, const double2* z, int32_t n_z, int32_t L, const double2* V,
                     const cbs_params* prm, hipStream_t st, NodeSolve& out);
 int32_t split_pairs(int64_t N, int32_t nruns, const Pair<double>* Y, double2* ya, double2* yb, hipStream_t st);
 int32_t check_params(const cbs_params* p, bool need_moments);
+void configure_solve(BicgSolve& b, const cbs_params* prm);
 
 }  // namespace cbs

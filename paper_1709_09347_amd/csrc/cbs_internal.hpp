@@ -70,16 +70,6 @@ struct alignas(2 * sizeof(cplx<R>)) Pair {
   cplx<R> b;  // dual
 };
 
-// ------------------------------------------------------------- run state
-enum RunStatus : int32_t {
-  RUN_ACTIVE = 0,
-  RUN_RU = 1,        // marked for a reliable update (FP64 residual replacement) this iteration
-  RUN_DONE = 2,      // converged (true FP64 residual below tol)
-  RUN_NOCONV = 3,    // stopped at max_iter
-  RUN_BREAKDOWN = 4, // rho or sigma vanished
-  RUN_HALTED = 5     // stopped by the half-of-the-nodes rule
-};
-
 // Coefficient triple of one vector: y = c0 (H0-E) x + cp H+ x + cm H- x.
 // Per run: [primal c0, cp, cm, dual c0, cp, cm] as complex doubles.
 struct RunCoef {
@@ -91,6 +81,15 @@ struct RunCoef {
 template <typename R> struct vec4;
 template <> struct vec4<double> { using T = double4; };
 template <> struct vec4<float> { using T = float4; };
+
+// Output layout of the 16x16x4 MFMA instructions (one block, 4 accumulators per lane,
+// column = lane % 16): the FP64 variant holds row 4*v + lane/16 in accumulator v, the
+// FP32 variant row 4*(lane/16) + v.  Operands: lane l feeds A[l%16][l/16] and
+// B[l/16][l%16] in both.
+template <typename R>
+__device__ __forceinline__ int mfma16_row(int lane, int v) {
+  return sizeof(R) == 8 ? 4 * v + (lane >> 4) : 4 * (lane >> 4) + v;
+}
 
 // Remap a block id so that consecutive logical blocks run on one XCD (the
 // dispatcher hands blocks to the 8 XCDs round-robin); gridDim must be a
@@ -156,6 +155,7 @@ struct DevBuf {
 struct Workspace {
   std::map<std::string, DevBuf> bufs;
   int32_t get(const char* name, size_t bytes, void** out);
+  void drop(const char* name);
   void release();
 };
 
@@ -209,6 +209,8 @@ struct cbs_system {
   cbs::Workspace ws;
   cbs::LastSolve last;
   int32_t tile_y[2] = {0, 0};       // stencil tile rows per precision (0 = double, 1 = float)
+  int32_t tuned = 0;                // tile heights picked by the autotuner
+  std::string tune_log;
 };
 
 namespace cbs {
@@ -236,17 +238,19 @@ int32_t launch_stencil(const cbs_system* s, bool bicg, const StencilLaunch& a, i
                        hipStream_t st);
 int32_t stencil_tiles(const cbs_system* s, int32_t tile_y);
 int32_t default_tile_y(const cbs_system* s, int32_t bytes_per_pair);
+// Times every feasible tile height once per system and precision (CBS_AUTOTUNE=0: keep defaults).
+int32_t autotune_tiles(cbs_system* s, hipStream_t st);
 
 // Nonlocal part: bra (coefficients of every atom) then ket tables.
 template <typename R>
 int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunCoef* coef,
                    const int32_t* status, int32_t need_status, void* kt, double2* signl,
-                   hipStream_t st);
+                   hipStream_t st, bool phased);
 
 // Fused pointwise kernels.
 template <typename R>
 int32_t launch_update(const cbs_system* s, int32_t nruns, void* r, const void* q, const void* kt,
-                      const double2* alpha, const int32_t* status, double* part,
+                      const double2* alpha, const int32_t* status, int32_t need_status, double* part,
                       int32_t nchunks, hipStream_t st);
 template <typename R>
 int32_t launch_ket_add(const cbs_system* s, int32_t nruns, void* q, const void* kt, hipStream_t st);

@@ -44,7 +44,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // One 16x16 complex tile of C = A^H B per workgroup (4 waves), over a slice of the long
 // axis.  MFMA f64 16x16x4: lane l feeds A[l%16][k=l/16] and B[k=l/16][l%16] and holds
-// D[4*(l/16)+v][l%16], v = 0..3.  The k slot of a lane walks 4 consecutive points of its
+// D[4*v + l/16][l%16], v = 0..3.  The k slot of a lane walks 4 consecutive points of its
 // vector over 4 instructions, so each lane streams 64 contiguous bytes per step.
 // C_re = Ar^T Br + Ai^T Bi, C_im = Ar^T Bi - Ai^T Br.
 __global__ void __launch_bounds__(256) k_gram_mfma(int64_t N, int32_t na, int32_t nb, const c64* A,
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(256) k_gram_mfma(int64_t N, int32_t na, int32_
     for (int v = 0; v < 4; ++v) {
       const double re = red[0][0][tid][v] + red[1][0][tid][v] + red[2][0][tid][v] + red[3][0][tid][v];
       const double im = red[0][1][tid][v] + red[1][1][tid][v] + red[2][1][tid][v] + red[3][1][tid][v];
-      const int i = ta * 16 + 4 * (tid >> 4) + v;
+      const int i = ta * 16 + mfma16_row<double>(tid, v);
       const int j = tb * 16 + (tid & 15);
       if (i < na && j < nb) {
         double* o = part + (((int64_t)sp * na + i) * nb + j) * 2;

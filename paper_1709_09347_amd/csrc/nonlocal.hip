@@ -23,7 +23,7 @@ namespace cbs {
 // ------------------------------------------------------------------------- bra
 template <typename R>
 struct BraArgs {
-  int32_t n_atoms, nlogical, need_status;
+  int32_t n_atoms, nlogical, need_status, nruns;
   int64_t N;
   const int32_t* seg;
   const int32_t* idx;
@@ -112,13 +112,137 @@ __global__ void __launch_bounds__(256) k_bra(BraArgs<R> a) {
   }
 }
 
+// MFMA bra for operators of the form P(z) (c0 = 1, cp = z, cm = 1/z per half): then
+// K[w][i] = h_ai z^-w c_ai with c_ai = sum_e u_{e,i} z^{w_e} v(idx_e), so the Bloch
+// phase is applied to the gathered vector and one contraction per atom remains:
+//   C[(run, half, re/im)][i] = sum_e A[(run, half, re/im)][e] U[e][i],
+// a [16 x n_ball] x [n_ball x 4] product per wave (4 runs x 2 halves x re/im rows),
+// 4 waves = 16 runs per workgroup sharing every table read.  MFMA 16x16x4: lane l
+// feeds A[l%16][k=l/16] and U[k=l/16][l%16] (columns 4..15 are zero padding) and holds
+// C[mfma16_row(l, v)][l%16].
+template <typename R> struct mf4;
+template <> struct mf4<double> { typedef double T __attribute__((ext_vector_type(4))); };
+template <> struct mf4<float> { typedef float T __attribute__((ext_vector_type(4))); };
+
+__device__ __forceinline__ mf4<double>::T mfma16x16x4(double a, double b, mf4<double>::T c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mf4<float>::T mfma16x16x4(float a, float b, mf4<float>::T c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
+  __shared__ cplx<R> cs[16][2][4];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (lb >= a.nlogical) return;
+  const int chunk = lb / a.n_atoms;
+  const int atom = lb - chunk * a.n_atoms;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int any = 0;
+  if (tid < 16) {
+    const int run = chunk * 16 + tid;
+    any = (run < a.nruns) && (a.status == nullptr || a.status[run] == a.need_status);
+  }
+  if (!__syncthreads_or(any)) return;
+  // Every wave covers all 16 runs (four groups g of 4 runs: four independent MFMA chains
+  // that share each table load) over every 4th step of 4 ball entries; the four waves'
+  // partial products are summed through LDS.
+  __shared__ R red[4][4][64][4];
+  const int row = lane & 15, kslot = lane >> 4, col = lane & 15;
+  const int half = (row >> 1) & 1, reim = row & 1;
+  const cplx<R>* vrow[4];
+  cplx<R> zp[4], zm[4];
+  bool rvalid[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int run = chunk * 16 + 4 * g + (row >> 2);
+    rvalid[g] = (run < a.nruns) && (a.status == nullptr || a.status[run] == a.need_status);
+    zp[g] = rvalid[g] ? ccast<R, double>(a.coef[run].c[3 * half + 1]) : mkc<R>(0, 0);
+    zm[g] = rvalid[g] ? ccast<R, double>(a.coef[run].c[3 * half + 2]) : mkc<R>(0, 0);
+    vrow[g] = reinterpret_cast<const cplx<R>*>(a.v + (int64_t)(rvalid[g] ? run : 0) * a.N) + half;
+  }
+  const int s0 = a.seg[4 * atom], s1 = a.seg[4 * atom + 1], s2 = a.seg[4 * atom + 2], s3 = a.seg[4 * atom + 3];
+  typename mf4<R>::T acc[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) acc[g] = {0, 0, 0, 0};
+  for (int e0 = s0 + 4 * wv; e0 < s3; e0 += 16) {
+    const int e = e0 + kslot;
+    const bool ok = e < s3;
+    int idx = 0;
+    R bv = 0;
+    if (ok) {
+      idx = a.idx[e];
+      if (col < 4) bv = a.u[4 * (int64_t)e + col];
+    }
+    cplx<R> vv[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) vv[g] = (ok && rvalid[g]) ? vrow[g][2 * (int64_t)idx] : mkc<R>(0, 0);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const cplx<R> p = (e < s1) ? cmul<R>(zm[g], vv[g]) : (e < s2) ? vv[g] : cmul<R>(zp[g], vv[g]);
+      acc[g] = mfma16x16x4(reim ? p.y : p.x, bv, acc[g]);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wv][g][lane][v] = acc[g][v];
+  __syncthreads();
+  {
+    // thread t < 256: group g = t/64 reduces lane t%64 over the four waves
+    const int g = tid >> 6, l2 = tid & 63;
+    if ((l2 & 15) < 4) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const R sum = red[0][g][l2][v] + red[1][g][l2][v] + red[2][g][l2][v] + red[3][g][l2][v];
+        const int r = mfma16_row<R>(l2, v);   // output row held by lane l2
+        R* dst = reinterpret_cast<R*>(&cs[4 * g + (r >> 2)][(r >> 1) & 1][l2 & 15]);
+        dst[r & 1] = sum;
+      }
+    }
+  }
+  __syncthreads();
+  const RunCoef* cfp = a.coef;
+  for (int t = tid; t < 16 * 24; t += 256) {
+    const int r2 = t / 24, rem = t - r2 * 24;
+    const int h2 = rem & 1, i = (rem >> 1) & 3, sw = rem >> 3;
+    const int rr = chunk * 16 + r2;
+    if (rr >= a.nruns || (a.status != nullptr && a.status[rr] != a.need_status)) continue;
+    const RunCoef& cf = cfp[rr];
+    // K[w][i] = h z^-w c: w = -1 -> cp, 0 -> c0, +1 -> cm
+    const cplx<R> f = ccast<R, double>(cf.c[3 * h2 + (sw == 0 ? 1 : sw == 1 ? 0 : 2)]);
+    const cplx<R> k = cscale<R>(cmul<R>(f, cs[r2][h2][i]), a.coeff[4 * atom + i]);
+    cplx<R>* dst = reinterpret_cast<cplx<R>*>(&a.kt[((int64_t)rr * a.n_atoms + atom) * 12 + sw * 4 + i]);
+    dst[h2] = k;
+  }
+  if (a.signl != nullptr && tid < 16) {
+    const int rr = chunk * 16 + tid;
+    if (rr < a.nruns && (a.status == nullptr || a.status[rr] == a.need_status)) {
+      double2 sg = make_double2(0.0, 0.0);
+      for (int i = 0; i < 4; ++i) {
+        const cplx<R> t = cscale<R>(cmulc<R>(cs[tid][1][i], cs[tid][0][i]), a.coeff[4 * atom + i]);
+        sg.x += (double)t.x;
+        sg.y += (double)t.y;
+      }
+      a.signl[(int64_t)rr * a.n_atoms + atom] = sg;
+    }
+  }
+}
+
+static bool bra_plain() {
+  const char* e = getenv("CBS_NO_MFMA");
+  return e && e[0] == '1';
+}
+
 template <typename R>
 int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunCoef* coef,
                    const int32_t* status, int32_t need_status, void* kt, double2* signl,
-                   hipStream_t st) {
+                   hipStream_t st, bool phased) {
   const Projector& pr = s->proj;
   if (pr.n_atoms == 0 || nruns <= 0) return CBS_OK;
   BraArgs<R> a;
+  a.nruns = nruns;
   a.n_atoms = pr.n_atoms;
   a.nlogical = nruns * pr.n_atoms;
   a.need_status = need_status;
@@ -132,8 +256,14 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
   a.status = status;
   a.kt = (Pair<R>*)kt;
   a.signl = signl;
-  const int grid = (a.nlogical + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_bra<R>, dim3(grid), dim3(256), 0, st, a);
+  if (phased && !bra_plain()) {
+    a.nlogical = ((nruns + 15) / 16) * pr.n_atoms;
+    const int grid = (a.nlogical + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_bra_mfma<R>, dim3(grid), dim3(256), 0, st, a);
+  } else {
+    const int grid = (a.nlogical + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_bra<R>, dim3(grid), dim3(256), 0, st, a);
+  }
   CBS_HIP(hipGetLastError());
   return CBS_OK;
 }
@@ -143,7 +273,7 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
 // rho = rt^H r, ||r||^2, ||rt||^2 per (run, chunk).
 template <typename R>
 struct UpdArgs {
-  int32_t nchunks, nlogical, n_atoms;
+  int32_t nchunks, nlogical, n_atoms, need_status, nruns;
   int64_t N, chunk;
   Pair<R>* r;
   const Pair<R>* q;
@@ -156,53 +286,95 @@ struct UpdArgs {
   double* part;   // [run][chunk][4]
 };
 
+// One workgroup updates UB consecutive runs over a chunk of points: each point's
+// projector entries (key, four values) are read once and reused for every run.
+constexpr int UB = 4;
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
-  __shared__ double red[4][4];
+  __shared__ double red[4][UB][4];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   if (lb >= a.nlogical) return;
-  const int run = lb / a.nchunks;
-  const int ch = lb - run * a.nchunks;
-  if (a.status[run] != RUN_ACTIVE) return;
+  const int rc = lb / a.nchunks;
+  const int ch = lb - rc * a.nchunks;
+  const int r0 = rc * UB;
+  bool act[UB];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < UB; ++k) {
+    act[k] = (r0 + k < a.nruns) && (a.status[r0 + k] == a.need_status);
+    any = any || act[k];
+  }
+  if (!any) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const double2 al = a.alpha[run];
-  const cplx<R> aa = mkc<R>((R)al.x, (R)al.y), ab = cconj<R>(aa);
-  const int64_t base = (int64_t)run * a.N;
-  const int64_t ktbase = (int64_t)run * a.n_atoms * 12;
+  cplx<R> aa[UB];
+#pragma unroll
+  for (int k = 0; k < UB; ++k) {
+    const double2 al = act[k] ? a.alpha[r0 + k] : make_double2(0, 0);
+    aa[k] = mkc<R>((R)al.x, (R)al.y);
+  }
   const int64_t lo = ch * a.chunk;
   const int64_t hi = (lo + a.chunk < a.N) ? lo + a.chunk : a.N;
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  double s[UB][4];
+#pragma unroll
+  for (int k = 0; k < UB; ++k) s[k][0] = s[k][1] = s[k][2] = s[k][3] = 0;
   for (int64_t n = lo + tid; n < hi; n += 256) {
-    Pair<R> q = a.q[base + n];
-    if (a.kt != nullptr) {
-      const Pair<R> k = ket_at<R>(n, ktbase, a.pt_off, a.pt_key, a.pt_u, a.kt);
-      q.a = cadd<R>(q.a, k.a);
-      q.b = cadd<R>(q.b, k.b);
+    Pair<R> kq[UB];
+#pragma unroll
+    for (int k = 0; k < UB; ++k) {
+      kq[k].a = mkc<R>(0, 0);
+      kq[k].b = kq[k].a;
     }
-    Pair<R> r = a.r[base + n];
-    r.a = csub<R>(r.a, cmul<R>(aa, q.a));
-    r.b = csub<R>(r.b, cmul<R>(ab, q.b));
-    a.r[base + n] = r;
-    const cplx<R> rho = cmulc<R>(r.b, r.a);
-    s0 += (double)rho.x;
-    s1 += (double)rho.y;
-    s2 += (double)cabs2<R>(r.a);
-    s3 += (double)cabs2<R>(r.b);
+    if (a.kt != nullptr) {
+      const int e0 = a.pt_off[n], e1 = a.pt_off[n + 1];
+      for (int e = e0; e < e1; ++e) {
+        const int key = a.pt_key[e];
+        const typename vec4<R>::T uu = reinterpret_cast<const typename vec4<R>::T*>(a.pt_u)[e];
+        const R us[4] = {uu.x, uu.y, uu.z, uu.w};
+        const int64_t off = (int64_t)(key >> 2) * 12 + (key & 3) * 4;
+#pragma unroll
+        for (int k = 0; k < UB; ++k) {
+          if (!act[k]) continue;
+          const Pair<R>* kt = a.kt + (int64_t)(r0 + k) * a.n_atoms * 12 + off;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const Pair<R> kk = kt[i];
+            kq[k].a = cfma_r<R>(kq[k].a, us[i], kk.a);
+            kq[k].b = cfma_r<R>(kq[k].b, us[i], kk.b);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < UB; ++k) {
+      if (!act[k]) continue;
+      const int64_t g = (int64_t)(r0 + k) * a.N + n;
+      Pair<R> q = a.q[g];
+      q.a = cadd<R>(q.a, kq[k].a);
+      q.b = cadd<R>(q.b, kq[k].b);
+      Pair<R> r = a.r[g];
+      r.a = csub<R>(r.a, cmul<R>(aa[k], q.a));
+      r.b = csub<R>(r.b, cmul<R>(cconj<R>(aa[k]), q.b));
+      a.r[g] = r;
+      const cplx<R> rho = cmulc<R>(r.b, r.a);
+      s[k][0] += (double)rho.x;
+      s[k][1] += (double)rho.y;
+      s[k][2] += (double)cabs2<R>(r.a);
+      s[k][3] += (double)cabs2<R>(r.b);
+    }
   }
-  s0 = wsum<double>(s0);
-  s1 = wsum<double>(s1);
-  s2 = wsum<double>(s2);
-  s3 = wsum<double>(s3);
-  if (lane == 0) {
-    red[wv][0] = s0;
-    red[wv][1] = s1;
-    red[wv][2] = s2;
-    red[wv][3] = s3;
-  }
+#pragma unroll
+  for (int k = 0; k < UB; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double t = wsum<double>(s[k][j]);
+      if (lane == 0) red[wv][k][j] = t;
+    }
   __syncthreads();
-  if (tid < 4) {
-    a.part[((int64_t)run * a.nchunks + ch) * 4 + tid] =
-        red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  if (tid < 4 * UB) {
+    const int k = tid >> 2, j = tid & 3;
+    if (act[k])
+      a.part[((int64_t)(r0 + k) * a.nchunks + ch) * 4 + j] = red[0][k][j] + red[1][k][j] + red[2][k][j] + red[3][k][j];
   }
 }
 
@@ -213,12 +385,14 @@ int32_t update_chunks(const cbs_system* s) {
 
 template <typename R>
 int32_t launch_update(const cbs_system* s, int32_t nruns, void* r, const void* q, const void* kt,
-                      const double2* alpha, const int32_t* status, double* part, int32_t nchunks,
-                      hipStream_t st) {
+                      const double2* alpha, const int32_t* status, int32_t need_status, double* part,
+                      int32_t nchunks, hipStream_t st) {
   if (nruns <= 0) return CBS_OK;
   UpdArgs<R> a;
+  a.need_status = need_status;
   a.nchunks = nchunks;
-  a.nlogical = nruns * nchunks;
+  a.nruns = nruns;
+  a.nlogical = ((nruns + UB - 1) / UB) * nchunks;
   a.n_atoms = s->proj.n_atoms;
   a.N = s->N;
   a.chunk = (s->N + nchunks - 1) / nchunks;
@@ -318,9 +492,9 @@ int32_t launch_from_pairs(int64_t N, int32_t nvec, const void* pairs, void* y, h
 
 #define INST(R)                                                                                   \
   template int32_t launch_bra<R>(const cbs_system*, int32_t, const void*, const RunCoef*,         \
-                                 const int32_t*, int32_t, void*, double2*, hipStream_t);          \
+                                 const int32_t*, int32_t, void*, double2*, hipStream_t, bool);    \
   template int32_t launch_update<R>(const cbs_system*, int32_t, void*, const void*, const void*,  \
-                                    const double2*, const int32_t*, double*, int32_t,             \
+                                    const double2*, const int32_t*, int32_t, double*, int32_t,    \
                                     hipStream_t);                                                 \
   template int32_t launch_ket_add<R>(const cbs_system*, int32_t, void*, const void*, hipStream_t); \
   template int32_t launch_to_pairs<R>(int64_t, int32_t, const void*, void*, hipStream_t);         \

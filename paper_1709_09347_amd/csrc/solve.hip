@@ -12,8 +12,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "bicg.hpp"
@@ -188,6 +191,21 @@ static int32_t vec_norms(int64_t N, int32_t nv, const c64* V, int64_t ldv, doubl
 
 static int32_t launch_grid(int64_t work) { return (int32_t)std::min<int64_t>((work + 255) / 256, 4096); }
 
+// Diagnostics: with CBS_DUMP=<dir>, intermediate arrays of the extraction are written
+// there as raw little-endian files (<name>.bin) for offline comparison.
+static void dump(const char* name, const void* dev, size_t bytes, hipStream_t st) {
+  const char* dir = getenv("CBS_DUMP");
+  if (!dir || !dir[0] || !dev || bytes == 0) return;
+  std::vector<char> h(bytes);
+  if (hipMemcpyAsync(h.data(), dev, bytes, hipMemcpyDeviceToHost, st) != hipSuccess) return;
+  if (hipStreamSynchronize(st) != hipSuccess) return;
+  std::string path = std::string(dir) + "/" + name + ".bin";
+  FILE* f = fopen(path.c_str(), "wb");
+  if (!f) return;
+  fwrite(h.data(), 1, bytes, f);
+  fclose(f);
+}
+
 struct Extracted {
   std::vector<c64> lam;      // candidates kept (in the annulus, residual-filtered), sorted
   std::vector<double> res;
@@ -229,6 +247,8 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
   }
   CBS_TRY(gram(s, N, L, V, N, nk * L, S, N, C, L, st));
   CBS_HIP(hipStreamSynchronize(st));
+  dump("S", S, (size_t)nk * L * N * sizeof(c64), st);
+  dump("mu", C, (size_t)L * nk * L * sizeof(c64), st);
   auto t1 = std::chrono::steady_clock::now();
   if (t_mom_ms) *t_mom_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
 
@@ -245,7 +265,13 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
   CBS_HIP(hipMemsetAsync(info, 0, 4 * sizeof(int32_t), st));
   hipLaunchKernelGGL(k_hankel, dim3(launch_grid((int64_t)n * n)), dim3(256), 0, st, L, M, (const c64*)C, T, Tl);
   CBS_HIP(hipGetLastError());
+  dump("T", T, (size_t)n * n * sizeof(c64), st);
+  dump("Tl", Tl, (size_t)n * n * sizeof(c64), st);
   CBS_TRY(svd(n, T, n, W, n, sig, perm, st));
+  dump("U", T, (size_t)n * n * sizeof(c64), st);
+  dump("W", W, (size_t)n * n * sizeof(c64), st);
+  dump("sigma", sig, (size_t)n * sizeof(double), st);
+  dump("perm", perm, (size_t)n * sizeof(int32_t), st);
   std::vector<double> hsig(n);
   CBS_HIP(hipMemcpyAsync(hsig.data(), sig, n * sizeof(double), hipMemcpyDeviceToHost, st));
   CBS_HIP(hipStreamSynchronize(st));
@@ -280,7 +306,10 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
   CBS_TRY(ws_get(ws, "hk.inv", (size_t)m, &dinv));
   CBS_HIP(hipMemcpyAsync(dinv, inv.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
   CBS_TRY(small_gemm(m, m, n, Up, n, true, TW, n, Bred, m, dinv, nullptr, st));
+  dump("Bred", Bred, (size_t)m * m * sizeof(c64), st);
   CBS_TRY(eig(s, m, Bred, m, tau, phi, m, info, st));
+  dump("tau", tau, (size_t)m * sizeof(c64), st);
+  dump("phi", phi, (size_t)m * m * sizeof(c64), st);
 
   std::vector<c64> cand;
   c64* basis = nullptr;   // N x ncand candidate vectors (not normalised)
@@ -340,8 +369,12 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
     hipLaunchKernelGGL(k_linearize, dim3(launch_grid((int64_t)n2 * n2)), dim3(256), 0, st, m, (const c64*)A3,
                        (const c64*)(A3 + (size_t)m * m), (const c64*)(A3 + (size_t)2 * m * m), sft, X, Bl);
     CBS_HIP(hipGetLastError());
+    dump("Q", Qa, (size_t)m * N * sizeof(c64), st);
+    dump("A3", A3, (size_t)3 * m * m * sizeof(c64), st);
     CBS_TRY(lu_solve(n2, X, n2, Bl, n2, n2, info, st));
+    dump("Minv", Bl, (size_t)n2 * n2 * sizeof(c64), st);
     CBS_TRY(eig(s, n2, Bl, n2, th, vv, n2, info, st));
+    dump("theta", th, (size_t)n2 * sizeof(c64), st);
     std::vector<c64> hth(n2);
     CBS_HIP(hipMemcpyAsync(hth.data(), th, n2 * sizeof(c64), hipMemcpyDeviceToHost, st));
     CBS_HIP(hipStreamSynchronize(st));
@@ -390,6 +423,15 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
   int32_t hinfo[4];
   CBS_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
   CBS_HIP(hipStreamSynchronize(st));
+  if (getenv("CBS_DUMP")) {
+    std::string dir = getenv("CBS_DUMP");
+    FILE* f = fopen((dir + "/cand.txt").c_str(), "w");
+    if (f) {
+      fprintf(f, "info %d %d %d %d\n", hinfo[0], hinfo[1], hinfo[2], hinfo[3]);
+      for (int i = 0; i < ncand; ++i) fprintf(f, "%.17g %.17g %.6e\n", cand[i].x, cand[i].y, rn[i]);
+      fclose(f);
+    }
+  }
   if (hinfo[0] == 1) {
     set_error("QR iteration of the reduced eigenproblem did not converge");
     return CBS_ENOCONV;
@@ -475,8 +517,8 @@ extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, con
   double mx = 0, sum = 0;
   int im = 0;
   for (int r = 0; r < ns.nruns; ++r) {
-    noconv = noconv || (ns.status[r] != RUN_DONE && ns.status[r] != RUN_HALTED);
-    brk = brk || ns.status[r] == RUN_BREAKDOWN;
+    noconv = noconv || (ns.status[r] != ST_DONE && ns.status[r] != ST_HALTED);
+    brk = brk || ns.status[r] == ST_BREAKDOWN;
     mx = std::max(mx, std::max(ns.relres[2 * r], ns.relres[2 * r + 1]));
     im = std::max(im, ns.iters[r]);
     sum += ns.iters[r];
@@ -497,7 +539,7 @@ extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, con
     info->t_moments_ms = tmom;
     info->t_extract_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() - tmom;
     info->matvecs = (int64_t)(2 * sum);
-    info->refine_steps = 0;
+    info->refine_steps = ns.n_ru;
     info->stencil_launches = ns.prof_launches;
     info->stencil_ms = ns.prof_ms;
     info->stencil_bytes = ns.prof_bytes;
@@ -527,4 +569,139 @@ extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, con
     return CBS_ERANK;
   }
   return CBS_OK;
+}
+
+// ------------------------------------------------------------------ batching
+// Every (system, energy) pair with the same parameters.  The BiCG runs of all
+// energies of a system form one batch (each run carries its own energy), and the
+// batches of all systems advance in the same captured graph, so one replay moves
+// every quadrature node, right-hand side, energy and grid of the wave.  Energies
+// are taken in waves sized to a device-memory budget (CBS_BATCH_BYTES, default 60%
+// of the free memory); the extraction then runs per (system, energy).
+extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, int32_t n_E, const double* E,
+                                     const cbs_params* prm, const void* const* V, int32_t max_eigs, double* lambda,
+                                     int32_t* n_eigs, cbs_info* info, void* stream) {
+  if (n_sys < 1 || !systems || n_E < 1 || !E || !V || max_eigs < 0 || (max_eigs > 0 && !lambda) || !n_eigs) {
+    set_error("cbs_solve_batched: bad argument");
+    return CBS_EINVAL;
+  }
+  CBS_TRY(check_params(prm, true));
+  for (int s = 0; s < n_sys; ++s) {
+    if (!systems[s] || !V[s] || systems[s]->device != systems[0]->device) {
+      set_error("cbs_solve_batched: null system/V or systems on different devices");
+      return CBS_EINVAL;
+    }
+  }
+  CBS_HIP(hipSetDevice(systems[0]->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int L = prm->n_rhs, nq = prm->n_q;
+  const bool mixed = prm->precision == CBS_MIXED;
+  // memory per energy for all systems
+  const double per_pt = mixed ? (5 * 16 + 5 * 32 + 32) : (5 * 32 + 32);
+  double per_energy = 0;
+  for (int s = 0; s < n_sys; ++s) per_energy += (double)systems[s]->N * nq * L * per_pt;
+  double budget = 0;
+  if (const char* e = getenv("CBS_BATCH_BYTES")) budget = atof(e);
+  if (!(budget > 0)) {
+    size_t fr = 0, tot = 0;
+    CBS_HIP(hipMemGetInfo(&fr, &tot));
+    budget = 0.6 * (double)fr;
+  }
+  const int wave = std::max(1, std::min(n_E, (int)(budget / per_energy)));
+  std::vector<c64> z1, w1, z2, w2;
+  quadrature(prm->lambda_min, nq, z1, w1, z2, w2);
+  int32_t worst = CBS_OK;
+  auto note = [&](int32_t rc) {
+    if (rc != CBS_OK && (worst == CBS_OK || rc == CBS_EBREAKDOWN)) worst = rc;
+  };
+  for (int e0 = 0; e0 < n_E; e0 += wave) {
+    const int ne = std::min(wave, n_E - e0);
+    std::vector<BicgSolve> solves(n_sys);
+    std::vector<std::vector<RunCoef>> coefs(n_sys);
+    std::vector<BicgSolve*> ptrs;
+    for (int s = 0; s < n_sys; ++s) {
+      cbs_system* sy = systems[s];
+      std::vector<RunCoef>& hc = coefs[s];
+      for (int e = 0; e < ne; ++e) {
+        std::vector<RunCoef> one;
+        node_coefs(z1.data(), nq, L, E[e0 + e], one);
+        hc.insert(hc.end(), one.begin(), one.end());
+      }
+      RunCoef* coef = nullptr;
+      CBS_TRY(ws_get(sy->ws, "batch.coef", hc.size(), &coef));
+      CBS_HIP(hipMemcpyAsync(coef, hc.data(), hc.size() * sizeof(RunCoef), hipMemcpyHostToDevice, st));
+      BicgSolve& b = solves[s];
+      b.sys = sy;
+      b.nruns = ne * nq * L;
+      b.L = L;
+      b.n_q = nq;
+      b.V = (const c64*)V[s];
+      b.coef = coef;
+      configure_solve(b, prm);
+      CBS_TRY(bicg_alloc(b, "bicg"));
+      ptrs.push_back(&b);
+    }
+    double ms = 0;
+    CBS_TRY(bicg_run(ptrs, st, prm->chunk, prm->max_iter, &ms, prm->profile != 0));
+    for (int s = 0; s < n_sys; ++s) {
+      cbs_system* sy = systems[s];
+      NodeSolve ns;
+      CBS_TRY(bicg_collect(solves[s], ns, st));
+      for (int e = 0; e < ne; ++e) {
+        const int ie = s * n_E + e0 + e;
+        Extracted ex;
+        double tmom = 0;
+        auto t0 = std::chrono::steady_clock::now();
+        const Pair<double>* Ye = ns.Y + (size_t)e * nq * L * sy->N;
+        int32_t rc = extract(sy, E[e0 + e], prm, (const c64*)V[s], Ye, st, ex, &tmom);
+        if (rc != CBS_OK) return rc;
+        auto t1 = std::chrono::steady_clock::now();
+        CBS_TRY(store_last(sy, E[e0 + e], ex, st));
+        const int cnt = (int)ex.lam.size();
+        n_eigs[ie] = cnt;
+        bool noconv = false, brk = false;
+        double mx = 0, sum = 0;
+        int im = 0;
+        for (int r = e * nq * L; r < (e + 1) * nq * L; ++r) {
+          noconv = noconv || (ns.status[r] != ST_DONE && ns.status[r] != ST_HALTED);
+          brk = brk || ns.status[r] == ST_BREAKDOWN;
+          mx = std::max(mx, std::max(ns.relres[2 * r], ns.relres[2 * r + 1]));
+          im = std::max(im, ns.iters[r]);
+          sum += ns.iters[r];
+        }
+        if (info) {
+          cbs_info& in = info[ie];
+          std::memset(&in, 0, sizeof(in));
+          in.rank = ex.rank;
+          in.n_eigs = cnt;
+          in.iters_max = im;
+          in.iters_mean = sum / (nq * L);
+          in.max_solve_resid = mx;
+          for (double r : ex.res) in.max_eig_resid = std::max(in.max_eig_resid, r);
+          in.sigma_first = ex.sig1;
+          in.sigma_ratio = ex.sig_ratio;
+          in.t_solve_ms = ms;   // shared by the whole wave
+          in.t_moments_ms = tmom;
+          in.t_extract_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() - tmom;
+          in.matvecs = (int64_t)(2 * sum);
+          in.refine_steps = ns.n_ru;
+        }
+        if (cnt > max_eigs) {
+          note(CBS_ETOOMANY);
+          continue;
+        }
+        double* out = lambda + (size_t)ie * 2 * max_eigs;
+        for (int k = 0; k < cnt; ++k) {
+          out[2 * k] = ex.lam[k].x;
+          out[2 * k + 1] = ex.lam[k].y;
+        }
+        if (brk) note(CBS_EBREAKDOWN);
+        else if (noconv) note(CBS_ENOCONV);
+        else if (ex.rank >= L * prm->n_mom) note(CBS_ERANK);
+      }
+    }
+  }
+  CBS_HIP(hipStreamSynchronize(st));
+  if (worst != CBS_OK) set_error("cbs_solve_batched: %s in at least one (system, energy) pair", cbs_strerror(worst));
+  return worst;
 }

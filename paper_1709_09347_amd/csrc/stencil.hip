@@ -314,3 +314,97 @@ template int32_t launch_stencil<float>(const cbs_system*, bool, const StencilLau
                                        hipStream_t);
 
 }  // namespace cbs
+
+namespace cbs {
+
+// ------------------------------------------------------------------ tile autotuner
+// Times the BiCG-mode stencil for every feasible tile height (full x rows, TY y rows,
+// double-buffered LDS when it fits) on a scratch batch of runs and keeps the fastest,
+// separately for complex128 and complex64.  Candidates are the heights with at most
+// 512 threads per workgroup and one plane buffer within 64 KB of LDS.
+template <typename R>
+static int32_t tune_one(cbs_system* s, hipStream_t st, int32_t* best_ty, std::string& log) {
+  const size_t per_run = (size_t)s->N * sizeof(Pair<R>);
+  int nr = (int)std::min<size_t>(256, std::max<size_t>(8, ((size_t)2 << 30) / (5 * per_run)));
+  Pair<R>* buf = nullptr;
+  RunCoef* coef = nullptr;
+  double2* sc = nullptr;
+  int32_t* status = nullptr;
+  double2* sig = nullptr;
+  CBS_TRY(ws_get(s->ws, "tune.buf", (size_t)5 * nr * s->N, &buf));
+  CBS_TRY(ws_get(s->ws, "tune.coef", (size_t)nr, &coef));
+  CBS_TRY(ws_get(s->ws, "tune.sc", (size_t)2 * nr, &sc));
+  CBS_TRY(ws_get(s->ws, "tune.status", (size_t)nr, &status));
+  CBS_TRY(ws_get(s->ws, "tune.sig", (size_t)nr * s->ny, &sig));
+  CBS_HIP(hipMemsetAsync(buf, 0, (size_t)5 * nr * per_run, st));
+  CBS_HIP(hipMemsetAsync(sc, 0, (size_t)2 * nr * sizeof(double2), st));
+  CBS_HIP(hipMemsetAsync(status, 0, (size_t)nr * sizeof(int32_t), st));
+  std::vector<RunCoef> hc(nr);
+  for (auto& c : hc) {
+    c.c[0] = c.c[3] = make_double2(1, 0);
+    c.c[1] = c.c[5] = make_double2(1.5, 1.0);
+    c.c[2] = c.c[4] = make_double2(0.4, -0.3);
+    c.E = 0.1;
+  }
+  CBS_HIP(hipMemcpyAsync(coef, hc.data(), nr * sizeof(RunCoef), hipMemcpyHostToDevice, st));
+  hipEvent_t e0, e1;
+  CBS_HIP(hipEventCreate(&e0));
+  CBS_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bty = default_tile_y(s, sizeof(Pair<R>));
+  for (int ty = 1; ty <= 16 && ty <= s->ny; ++ty) {
+    if (s->nx * ty > 512) break;
+    if ((size_t)(ty + 2 * s->p) * s->nx * sizeof(Pair<R>) > 64 * 1024) break;
+    StencilLaunch l{};
+    l.nruns = nr;
+    l.rin = buf;
+    l.pold = buf + (size_t)nr * s->N;
+    l.pnew = buf + (size_t)2 * nr * s->N;
+    l.q = buf + (size_t)3 * nr * s->N;
+    l.x = buf + (size_t)4 * nr * s->N;
+    l.coef = coef;
+    l.beta = sc;
+    l.xcoef = sc + nr;
+    l.status = status;
+    l.need_status = 0;
+    l.sig_part = sig;
+    int32_t rc = launch_stencil<R>(s, true, l, ty, st);
+    if (rc != CBS_OK) continue;
+    CBS_HIP(hipEventRecord(e0, st));
+    for (int k = 0; k < 3; ++k) CBS_TRY(launch_stencil<R>(s, true, l, ty, st));
+    CBS_HIP(hipEventRecord(e1, st));
+    CBS_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    CBS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    char line[96];
+    snprintf(line, sizeof(line), "%s ty=%d %.4f ms; ", sizeof(R) == 8 ? "c128" : "c64", ty, ms / 3);
+    log += line;
+    if (ms < best) {
+      best = ms;
+      bty = ty;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *best_ty = bty;
+  return CBS_OK;
+}
+
+int32_t autotune_tiles(cbs_system* s, hipStream_t st) {
+  if (s->tuned) return CBS_OK;
+  const char* e = getenv("CBS_AUTOTUNE");
+  if (e && e[0] == '0') {
+    s->tuned = 1;
+    return CBS_OK;
+  }
+  std::string log;
+  CBS_TRY(tune_one<double>(s, st, &s->tile_y[0], log));
+  CBS_TRY(tune_one<float>(s, st, &s->tile_y[1], log));
+  CBS_HIP(hipStreamSynchronize(st));
+  for (const char* n : {"tune.buf", "tune.coef", "tune.sc", "tune.status", "tune.sig"}) s->ws.drop(n);
+  s->tune_log = log;
+  s->tuned = 1;
+  return CBS_OK;
+}
+
+}  // namespace cbs

@@ -44,6 +44,13 @@ int32_t Workspace::get(const char* name, size_t bytes, void** out) {
   return CBS_OK;
 }
 
+void Workspace::drop(const char* name) {
+  auto it = bufs.find(name);
+  if (it == bufs.end()) return;
+  if (it->second.p) (void)hipFree(it->second.p);
+  bufs.erase(it);
+}
+
 void Workspace::release() {
   for (auto& kv : bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
@@ -222,7 +229,7 @@ int32_t apply_parts_dev(cbs_system* s, double E, int32_t n_vec, const double2* c
   const int32_t ty = s->tile_y[0] ? s->tile_y[0] : default_tile_y(s, sizeof(Pair<double>));
   CBS_TRY(launch_stencil<double>(s, false, l, ty, st));
   if (s->proj.n_atoms > 0) {
-    CBS_TRY(launch_bra<double>(s, nr, px, coef, nullptr, 0, kt, nullptr, st));
+    CBS_TRY(launch_bra<double>(s, nr, px, coef, nullptr, 0, kt, nullptr, st, false));
     CBS_TRY(launch_ket_add<double>(s, nr, pq, kt, st));
   }
   CBS_TRY(launch_from_pairs<double>(s->N, n_vec, pq, y, st));
@@ -272,7 +279,7 @@ static int32_t apply_z(cbs_system* s, double E, int32_t n_vec, const double* z, 
   const int32_t ty = s->tile_y[std::is_same<R, double>::value ? 0 : 1];
   CBS_TRY(launch_stencil<R>(s, false, l, ty ? ty : default_tile_y(s, sizeof(Pair<R>)), st));
   if (s->proj.n_atoms > 0) {
-    CBS_TRY(launch_bra<R>(s, nr, px, coef, nullptr, 0, kt, nullptr, st));
+    CBS_TRY(launch_bra<R>(s, nr, px, coef, nullptr, 0, kt, nullptr, st, true));
     CBS_TRY(launch_ket_add<R>(s, nr, pq, kt, st));
   }
   CBS_TRY(launch_from_pairs<R>(s->N, n_vec, pq, y, st));
@@ -314,7 +321,7 @@ void cbs_params_default(cbs_params* p) {
   p->precision = CBS_FP64;
   p->extraction = CBS_RR;
   p->half_stop = 0;
-  p->inner_tol = 1e-3;
+  p->inner_tol = 1e-4;
   p->max_refine = 60;
   p->chunk = 8;
 }
@@ -393,6 +400,15 @@ int32_t cbs_system_set_vloc(cbs_system* s, const double* v_loc) {
 }
 
 int64_t cbs_system_npoints(const cbs_system* s) { return s ? s->N : -1; }
+
+const char* cbs_system_tiling(const cbs_system* s, int32_t* tile_y) {
+  if (!s) return "";
+  if (tile_y) {
+    tile_y[0] = s->tile_y[0];
+    tile_y[1] = s->tile_y[1];
+  }
+  return s->tune_log.c_str();
+}
 
 int32_t cbs_apply(cbs_system* s, double E, int32_t n_vec, const double* z, int32_t dtype,
                   const void* x, void* y, void* stream) {
