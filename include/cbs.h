@@ -99,11 +99,13 @@ typedef struct {
   double delta;         /* SVD rank threshold, relative to the largest singular value */
   double tol;           /* per-column relative residual of every solve (primal and dual) */
   int32_t max_iter;     /* BiCG iteration cap (per inner solve) */
-  int32_t precision;    /* CBS_FP64 or CBS_MIXED (complex64 BiCG + FP64 refinement) */
+  int32_t precision;    /* CBS_FP64, or CBS_MIXED: complex128 BiCG until a run's residual is
+                           below inner_tol, then complex64 vectors and operator applications
+                           with FP64 residual replacement (iterative refinement) to tol */
   int32_t extraction;   /* CBS_RR (default) or CBS_HANKEL */
   int32_t half_stop;    /* 1: stop all solves once more than half of the nodes converged (Sec. 3.3) */
-  double inner_tol;     /* CBS_MIXED: relative tolerance of each complex64 inner solve */
-  int32_t max_refine;   /* CBS_MIXED: cap on FP64 refinement steps */
+  double inner_tol;     /* CBS_MIXED: residual below which a run continues in complex64 (1e-3) */
+  int32_t max_refine;   /* CBS_MIXED: cap on FP64 residual replacements per run (60) */
   int32_t chunk;        /* iterations per captured graph between convergence polls (even) */
   int32_t profile;      /* 1: no graph; HIP events time every BiCG stencil launch (cbs_info.stencil_*) */
 } cbs_params;

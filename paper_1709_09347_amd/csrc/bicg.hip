@@ -17,13 +17,17 @@
 //       and replaces r; the search direction is kept, so the Krylov space is not
 //       restarted.
 //   S3  decisions on the true residual (done / continue / change phase), active counts.
-// Precision (mixed mode): runs start with complex64 vectors; a replacement is triggered
-// whenever the recursive residual has dropped by `ru_factor` since the last one (the
-// FP64 iterative refinement of the single-precision recurrence); once the true residual
-// is below `switch_tol` the run's search direction is widened to complex128 and the
-// same recurrence finishes in complex128 (the complex64 recurrence converges almost as
-// fast as the complex128 one down to ~1e-4 and slows down beyond).  FP64 mode starts in
-// the complex128 phase, where S2 only marks runs whose recursive residual met tol.
+// Precision (mixed mode) follows the relaxation of inexact Krylov methods: the error
+// allowed in an operator application grows as the residual shrinks.  Every run starts
+// with complex128 vectors; once its residual is below `narrow_tol` its vectors are
+// rounded to complex64 and the same recurrence continues in single precision (the
+// search direction is kept, so the Krylov space is not restarted).  In that phase a
+// replacement is triggered whenever the recursive residual has dropped by `ru_factor`
+// since the last one: the FP64 iterative refinement that keeps the gap between the
+// single-precision recursive residual and the true residual below the tolerance.  A run
+// whose true residual stops falling in complex64 is widened back to complex128.  FP64
+// mode stays in the complex128 phase, where S2 only marks runs whose recursive residual
+// met tol.
 // The iteration is captured once into a HIP graph of `chunk` iterations and replayed
 // until no run is active.
 #include <algorithm>
@@ -197,6 +201,43 @@ __global__ void __launch_bounds__(256) k_widen(int64_t N, int32_t nchunks, int32
   }
 }
 
+// Narrow the runs that entered the complex64 phase this iteration (conv == 2): r and
+// the latest search direction are rounded to complex64, the complex128 iterate is
+// accumulated into y and both iterates restart from zero.
+__global__ void __launch_bounds__(256) k_narrow(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* conv,
+                                                const Pair<double>* Rhi, const Pair<double>* Phi, Pair<double>* Xhi,
+                                                Pair<float>* Rlo, Pair<float>* Plo, Pair<float>* Xlo,
+                                                Pair<double>* Y) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (lb >= nlogical) return;
+  const int run = lb / nchunks, ch = lb - run * nchunks;
+  if (conv[run] != 2) return;
+  const int64_t chunk = (N + nchunks - 1) / nchunks;
+  const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
+  for (int64_t n = lo + threadIdx.x; n < hi; n += 256) {
+    const int64_t g = (int64_t)run * N + n;
+    const Pair<double> r = Rhi[g], p = Phi[g], x = Xhi[g];
+    Pair<float> rf, pf, zf;
+    rf.a = ccast<float, double>(r.a);
+    rf.b = ccast<float, double>(r.b);
+    pf.a = ccast<float, double>(p.a);
+    pf.b = ccast<float, double>(p.b);
+    zf.a = mkc<float>(0, 0);
+    zf.b = zf.a;
+    Rlo[g] = rf;
+    Plo[g] = pf;
+    Xlo[g] = zf;
+    Pair<double> y = Y[g];
+    y.a = cadd<double>(y.a, x.a);
+    y.b = cadd<double>(y.b, x.b);
+    Y[g] = y;
+    Pair<double> zd;
+    zd.a = make_double2(0, 0);
+    zd.b = zd.a;
+    Xhi[g] = zd;
+  }
+}
+
 // ------------------------------------------------------------------ scalar kernels
 __device__ __forceinline__ bool finite2(double2 v) { return isfinite(v.x) && isfinite(v.y); }
 
@@ -210,7 +251,7 @@ __device__ __forceinline__ bool is_active(int st) { return st == ST_ACT_LO || st
 __device__ __forceinline__ bool is_ru(int st) { return st == ST_RU_LO || st == ST_RU_HI; }
 
 __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
-                                            int32_t start, double ru_factor) {
+                                            int32_t start) {
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
     double s[4];
     sum_part(part, (int64_t)run * nchunks, nchunks, s);
@@ -225,7 +266,7 @@ __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t 
     sc.brk[run] = 0;
     sc.halt[run] = 0;
     sc.conv[run] = 0;
-    sc.ru_thr[run] = (start == ST_ACT_LO) ? ru_factor : 0.0;
+    sc.ru_thr[run] = 0.0;
     const bool zero = !(s[2] > 0);
     sc.relres[2 * run] = zero ? 0.0 : 1.0;
     sc.relres[2 * run + 1] = zero ? 0.0 : 1.0;
@@ -266,7 +307,7 @@ __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t 
 }
 
 __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
-                                            double tol, int32_t max_iter) {
+                                            double tol, int32_t max_iter, double narrow_tol, double ru_factor) {
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
     const int st = sc.status[run];
     if (!is_active(st)) continue;
@@ -286,14 +327,19 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
     sc.beta[run] = bad ? make_double2(0, 0) : cdiv<double>(rn, ro);
     sc.rho_prev[run] = ro;
     sc.rho[run] = rn;
-    if (conv || bad || it >= max_iter || fmax(rr, rrt) < sc.ru_thr[run])
+    if (conv || bad || it >= max_iter || fmax(rr, rrt) < sc.ru_thr[run]) {
       sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
+    } else if (st == ST_ACT_HI && narrow_tol > 0.0 && sc.ru_thr[run] >= 0.0 && fmax(rr, rrt) < narrow_tol) {
+      // the residual is small enough for complex64 vectors and operator applications
+      sc.status[run] = ST_ACT_LO;
+      sc.conv[run] = 2;
+      sc.ru_thr[run] = fmax(rr, rrt) * ru_factor;
+    }
   }
 }
 
 __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
-                                            double tol, int32_t max_iter, int32_t max_ru, double ru_factor,
-                                            double switch_tol) {
+                                            double tol, int32_t max_iter, int32_t max_ru, double ru_factor) {
   __shared__ int cnt[2][4];
   int act_lo = 0, act_hi = 0;
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
@@ -320,16 +366,19 @@ __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t 
       } else {
         sc.beta[run] = cdiv<double>(rn, sc.rho_prev[run]);
         sc.rho[run] = rn;
-        if (st == ST_RU_LO && fmax(rr, rrt) <= switch_tol) {
-          st = ST_ACT_HI;   // finish the same recurrence in complex128
+        const double tr = fmax(rr, rrt);
+        if (st == ST_RU_LO && tr > 0.5 * sc.ru_thr[run] / ru_factor) {
+          // the complex64 recurrence stopped reducing the true residual: finish in
+          // complex128 (the replaced residual is in R64, the search direction is widened)
+          st = ST_ACT_HI;
           sc.conv[run] = 1;
-          sc.ru_thr[run] = 0.0;
+          sc.ru_thr[run] = -1.0;
         } else if (st == ST_RU_LO) {
           st = ST_ACT_LO;
-          sc.ru_thr[run] = fmax(rr, rrt) * ru_factor;
+          sc.ru_thr[run] = tr * ru_factor;
         } else {
           st = ST_ACT_HI;
-          sc.ru_thr[run] = 0.0;
+          sc.ru_thr[run] = (sc.ru_thr[run] < 0.0) ? -1.0 : 0.0;
         }
       }
       sc.status[run] = st;
@@ -433,21 +482,12 @@ static int32_t enqueue_init(BicgSolve& b, hipStream_t st) {
   hipLaunchKernelGGL(k_bicg_init<double>, dim3(g), dim3(256), 0, st, s->N, b.nruns, b.L, b.V, b.Vd ? b.Vd : b.V, b.hi.R, b.hi.Pb[0],
                      b.hi.Pb[1], b.hi.X, b.Y);
   CBS_HIP(hipGetLastError());
-  if (b.mixed) {
-    hipLaunchKernelGGL(k_bicg_init<float>, dim3(g), dim3(256), 0, st, s->N, b.nruns, b.L, b.V, b.Vd ? b.Vd : b.V, b.lo.R, b.lo.Pb[0],
-                       b.lo.Pb[1], b.lo.X, (Pair<double>*)nullptr);
-    CBS_HIP(hipGetLastError());
-  }
   const int nl = b.nruns * b.nchunks;
-  if (b.mixed)
-    hipLaunchKernelGGL(k_partials<float>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl,
-                       (const Pair<float>*)b.lo.R, b.upd_part);
-  else
-    hipLaunchKernelGGL(k_partials<double>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl,
-                       (const Pair<double>*)b.hi.R, b.upd_part);
+  hipLaunchKernelGGL(k_partials<double>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl,
+                     (const Pair<double>*)b.hi.R, b.upd_part);
   CBS_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_s0, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.upd_part,
-                     (int32_t)(b.mixed ? ST_ACT_LO : ST_ACT_HI), b.ru_factor);
+                     (int32_t)ST_ACT_HI);
   CBS_HIP(hipGetLastError());
   return CBS_OK;
 }
@@ -491,7 +531,7 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
   CBS_TRY(launch_update<double>(s, b.nruns, b.hi.R, b.hi.Q, b.hi.KT, b.sc.alpha, b.sc.status, ST_ACT_HI,
                                 b.upd_part, b.nchunks, st));
   hipLaunchKernelGGL(k_s2, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.upd_part, b.tol,
-                     b.max_iter);
+                     b.max_iter, b.narrow_tol, b.ru_factor);
   CBS_HIP(hipGetLastError());
   if (b.half_stop && b.n_q > 0) {
     hipLaunchKernelGGL(k_half_stop, dim3(1), dim3(256), 0, st, b.sc, b.nruns / (b.n_q * b.L), b.n_q, b.L);
@@ -529,11 +569,14 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
                      b.hi.R, (Pair<double>*)nullptr, b.ru_part);
   CBS_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_s3, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.ru_part, b.tol,
-                     b.max_iter, b.max_ru, b.ru_factor, b.switch_tol);
+                     b.max_iter, b.max_ru, b.ru_factor);
   CBS_HIP(hipGetLastError());
   if (b.mixed) {
     hipLaunchKernelGGL(k_widen, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, (const int32_t*)b.sc.conv,
                        (const Pair<float>*)b.lo.Pb[parity & 1], b.hi.Pb[parity & 1]);
+    hipLaunchKernelGGL(k_narrow, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, (const int32_t*)b.sc.conv,
+                       (const Pair<double>*)b.hi.R, (const Pair<double>*)b.hi.Pb[parity & 1], b.hi.X, b.lo.R,
+                       b.lo.Pb[parity & 1], b.lo.X, b.Y);
     hipLaunchKernelGGL(k_clear_conv, dim3(1), dim3(256), 0, st, b.sc, b.nruns);
     CBS_HIP(hipGetLastError());
   }
@@ -552,8 +595,8 @@ static int32_t run_profiled(std::vector<BicgSolve*>& solves, hipStream_t st, int
   std::vector<int32_t> act(2 * solves.size());
   for (size_t i = 0; i < solves.size(); ++i) {
     BicgSolve& b = *solves[i];
-    act[2 * i] = b.mixed ? b.nruns : 0;
-    act[2 * i + 1] = b.mixed ? 0 : b.nruns;
+    act[2 * i] = 0;
+    act[2 * i + 1] = b.nruns;
     CBS_HIP(hipEventCreate(&b.hi.ev0));
     CBS_HIP(hipEventCreate(&b.hi.ev1));
     if (b.mixed) {
@@ -758,8 +801,8 @@ int32_t split_pairs(int64_t N, int32_t nruns, const Pair<double>* Y, double2* ya
 void configure_solve(BicgSolve& b, const cbs_params* prm) {
   b.mixed = prm->precision == CBS_MIXED;
   b.tol = prm->tol;
-  b.ru_factor = 0.1;
-  b.switch_tol = b.mixed ? std::max(prm->inner_tol, prm->tol) : 0.0;
+  b.ru_factor = 1e-2;
+  b.narrow_tol = b.mixed ? std::max(prm->inner_tol, prm->tol) : 0.0;
   b.max_iter = prm->max_iter;
   b.max_ru = b.mixed ? std::max(prm->max_refine, 1) : (1 << 30);
   b.half_stop = prm->half_stop;

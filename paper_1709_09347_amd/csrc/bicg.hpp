@@ -11,7 +11,7 @@ namespace cbs {
 // high-precision phase (complex128); the state encodes the phase so every kernel
 // filters its runs with one comparison.
 enum BicgState : int32_t {
-  ST_ACT_LO = 0,   // iterating in complex64
+  ST_ACT_LO = 0,   // iterating in complex64 (residual already small)
   ST_RU_LO = 1,    // complex64 run marked for a residual replacement this iteration
   ST_DONE = 2,     // true complex128 residual below tol (primal and dual)
   ST_NOCONV = 3,   // iteration or replacement cap reached
@@ -30,13 +30,13 @@ struct BicgScal {
   double2* rho_prev;
   double* vn2;        // ||v||^2 of the run's right-hand side
   double* relres;     // [2*run]: primal, dual relative residual (last known)
-  double* ru_thr;     // next replacement when the recursive residual falls below this
+  double* ru_thr;     // complex64 phase: next replacement below this; -1: kept in complex128
   int32_t* status;
   int32_t* iters;
   int32_t* brk;
   int32_t* halt;
   int32_t* nru;
-  int32_t* conv;      // 1: switched to complex128 this iteration, search direction to convert
+  int32_t* conv;      // phase change this iteration: 1 widen to complex128, 2 narrow to complex64
   int32_t* n_active;  // [2]: active runs in the complex64 / complex128 phase
 };
 
@@ -71,7 +71,7 @@ struct BicgSolve {
   double* upd_part = nullptr;
   double* ru_part = nullptr;
   BicgScal sc{};
-  double tol = 1e-10, ru_factor = 0.1, switch_tol = 1e-4;
+  double tol = 1e-10, ru_factor = 1e-2, narrow_tol = 0.0;
   int32_t max_iter = 10000, max_ru = 1000, half_stop = 0;
 };
 

@@ -449,11 +449,20 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
     if (!(rn[i] <= keep_tol)) continue;
     idx.push_back(i);
   }
-  std::sort(idx.begin(), idx.end(), [&](int a, int b) {
-    const double la = std::fabs(std::log(sqrt(cabs2<double>(cand[a])))), lb = std::fabs(std::log(sqrt(cabs2<double>(cand[b]))));
-    if (la != lb) return la < lb;
-    return atan2(cand[a].y, cand[a].x) < atan2(cand[b].y, cand[b].x);
-  });
+  // Order: decay |ln|lambda|| (propagating modes first), then the Bloch phase arg(lambda),
+  // then |lambda| (the inner partner of a pair lambda, 1/conj(lambda) before the outer
+  // one).  Values equal to 1e-9 count as ties, so partners whose |ln|lambda|| differ only
+  // by rounding keep a stable order; insertion sort, which needs no strict weak order.
+  auto before = [&](int a, int b) {
+    const double aa = sqrt(cabs2<double>(cand[a])), ab = sqrt(cabs2<double>(cand[b]));
+    const double la = std::fabs(std::log(aa)), lb = std::fabs(std::log(ab));
+    if (std::fabs(la - lb) > 1e-9 * (1.0 + std::max(la, lb))) return la < lb;
+    const double pa = atan2(cand[a].y, cand[a].x), pb = atan2(cand[b].y, cand[b].x);
+    if (std::fabs(pa - pb) > 1e-9) return pa < pb;
+    return aa < ab;
+  };
+  for (size_t i = 1; i < idx.size(); ++i)
+    for (size_t j = i; j > 0 && before(idx[j], idx[j - 1]); --j) std::swap(idx[j], idx[j - 1]);
   out.lam.resize(idx.size());
   out.res.resize(idx.size());
   CBS_TRY(ws_get(ws, "ex.out", std::max<size_t>(idx.size(), 1) * N, &out.vecs));

@@ -321,7 +321,7 @@ void cbs_params_default(cbs_params* p) {
   p->precision = CBS_FP64;
   p->extraction = CBS_RR;
   p->half_stop = 0;
-  p->inner_tol = 1e-4;
+  p->inner_tol = 1e-3;
   p->max_refine = 60;
   p->chunk = 8;
 }

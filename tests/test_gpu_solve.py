@@ -1,10 +1,13 @@
 """The whole method at one energy (Algorithm 1 on the ring contour) against the oracle.
 
-Bars (complex128 result of record, Rayleigh-Ritz extraction): every eigenvalue of
-the dense QZ oracle inside the annulus is found, |dlambda|/|lambda| <= 1e-8, and
-every returned pair has ||P(lambda) psi|| / ||psi|| <= 1e-10 (recomputed by the
-oracle).  Hankel-only extraction is held to 1e-6 (its accuracy is limited by the
-SVD truncation, paper Sec. 4.1 reports 1e-5 for real k).
+Bars (Rayleigh-Ritz extraction): every eigenvalue of the dense QZ oracle inside the
+annulus is found, |dlambda|/|lambda| <= 1e-8, and every returned pair has
+||P(lambda) psi|| / ||psi|| <= 1e-10 (recomputed by the oracle) when the linear
+solves are refined to a 1e-12 relative residual.  At the paper's BiCG criterion
+(1e-10) the eigenpair residual is 10-50x the solve tolerance, in the oracle as on the
+device (the moments carry the solve error), so that case is held to 1e-8.
+Hankel-only extraction is held to 1e-6 (its accuracy is limited by the SVD
+truncation, paper Sec. 4.1 reports 1e-5 for real k).
 """
 import numpy as np
 import pytest
@@ -15,11 +18,15 @@ from oracle import ham, qep
 pytestmark = pytest.mark.gpu
 
 
+REFINED = 1e-12   # solve tolerance for the 1e-10 eigenpair-residual bar
+
+
 def _gpu_solve(sysw, E, cuda, L=8, M=8, seed=3, **kw):
     import torch
     import paper_1709_09347_amd as cbs
     s = cbs.System.from_workload(sysw)
     V = torch.from_numpy(W.make_rhs(sysw.n, L, seed)).to(cuda)
+    kw.setdefault("tol", REFINED)
     prm = cbs.default_params(n_rhs=L, n_mom=M, **kw)
     lam, vecs, res, info, rc = s.solve(E, V, prm)
     print(f"{sysw.name} E={E} prec={prm.precision} ext={prm.extraction}: {len(lam)} eigs, rank {info.rank}, "
@@ -28,13 +35,13 @@ def _gpu_solve(sysw, E, cuda, L=8, M=8, seed=3, **kw):
     return lam, (vecs.cpu().numpy() if vecs is not None else None), res, info, rc
 
 
-def _check_against(ref_lam, lam, vecs, res, H, E, tol=1e-8, ref_vecs=None):
+def _check_against(ref_lam, lam, vecs, res, H, E, tol=1e-8, ref_vecs=None, res_bar=1e-10):
     assert len(lam) == len(ref_lam), (lam, ref_lam)
     assert qep.match_sets(lam, ref_lam) <= tol
-    assert res.max() <= 1e-10
+    assert res.max() <= res_bar
     for i, l in enumerate(lam):
         r = np.linalg.norm(H.apply(l, vecs[i], E)) / np.linalg.norm(vecs[i])
-        assert r <= 1e-10, (l, r)
+        assert r <= res_bar, (l, r)
     if ref_vecs is not None:
         for i, l in enumerate(lam):
             j = int(np.argmin(np.abs(ref_lam - l)))
@@ -79,6 +86,18 @@ def test_solve_cfg1(cuda, E):
     assert qep.match_sets(lam2, ref.lam) <= 1e-8
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_cfg1_paper_criterion(cuda, precision):
+    # solves to the paper's 1e-10 criterion: eigenvalues to 1e-8, residuals to 1e-8
+    sysw = W.config(1).systems[0]
+    H = ham.build(sysw)
+    h0, hp, hm = H.blocks_dense()
+    ref = qep.solve_dense(h0, hp, hm, 0.3, 0.5, left=False)
+    lam, vecs, res, info, rc = _gpu_solve(sysw, 0.3, cuda, precision=precision, tol=1e-10)
+    assert rc == 0 and info.max_solve_resid <= 1e-10
+    _check_against(ref.lam, lam, vecs, res, H, 0.3, res_bar=1e-8)
+
+
 def test_solve_cfg1_mixed(cuda):
     sysw = W.config(1).systems[0]
     H = ham.build(sysw)
@@ -115,7 +134,7 @@ def test_solve_cfg2_full_size_invariants(cuda, precision):
     sysw = W.config(2).systems[0]
     H = ham.build(sysw)
     lam, vecs, res, info, rc = _gpu_solve(sysw, 0.2, cuda, L=16, M=8, precision=precision, seed=3002)
-    assert rc == 0 and len(lam) > 0
+    assert rc == 0 and len(lam) > 0 and info.max_solve_resid <= REFINED
     assert qep.match_sets(lam, 1 / np.conj(lam)) <= 1e-8
     assert qep.match_sets(lam, np.conj(lam)) <= 1e-8
     for i, l in enumerate(lam):
