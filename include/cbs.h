@@ -55,7 +55,8 @@ enum {
   CBS_ENOCONV = -4,     /* a linear solve missed its tolerance (results written) */
   CBS_EBREAKDOWN = -5,  /* BiCG breakdown (zero rho or sigma) */
   CBS_ERANK = -6,       /* Hankel rank reached L*M: subspace too small (results written) */
-  CBS_ETOOMANY = -7     /* more eigenvalues than max_eigs (count written) */
+  CBS_ETOOMANY = -7,    /* more eigenvalues than max_eigs (count written) */
+  CBS_ENONFINITE = -8   /* non-finite moments (a linear solve diverged); no eigenpairs */
 };
 
 enum { CBS_C128 = 0, CBS_C64 = 1 };          /* element type of cbs_apply vectors */
@@ -105,7 +106,7 @@ typedef struct {
   int32_t extraction;   /* CBS_RR (default) or CBS_HANKEL */
   int32_t half_stop;    /* 1: stop all solves once more than half of the nodes converged (Sec. 3.3) */
   double inner_tol;     /* CBS_MIXED: residual below which a run continues in complex64 (1e-3) */
-  int32_t max_refine;   /* CBS_MIXED: cap on FP64 residual replacements per run (60) */
+  int32_t max_refine;   /* cap on FP64 residual replacements per run (60) */
   int32_t chunk;        /* iterations per captured graph between convergence polls (even) */
   int32_t profile;      /* 1: no graph; HIP events time every BiCG stencil launch (cbs_info.stencil_*) */
 } cbs_params;

@@ -17,8 +17,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcbs.so")
 
-CBS_OK, CBS_EINVAL, CBS_ENOMEM, CBS_EHIP, CBS_ENOCONV, CBS_EBREAKDOWN, CBS_ERANK, CBS_ETOOMANY = \
-    0, -1, -2, -3, -4, -5, -6, -7
+CBS_OK, CBS_EINVAL, CBS_ENOMEM, CBS_EHIP, CBS_ENOCONV, CBS_EBREAKDOWN, CBS_ERANK, CBS_ETOOMANY, \
+    CBS_ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 CBS_C128, CBS_C64 = 0, 1
 CBS_FP64, CBS_MIXED = 0, 1
 CBS_RR, CBS_HANKEL = 0, 1

@@ -182,13 +182,13 @@ __global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int
   if (tid < 4) part[((int64_t)run * nchunks + ch) * 4 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
-// Widen the search direction of runs that changed phase this iteration.
+// Widen the search direction of runs that went back to complex128 this iteration (conv == 1).
 __global__ void __launch_bounds__(256) k_widen(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* conv,
                                                const Pair<float>* Plo, Pair<double>* Phi) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   if (lb >= nlogical) return;
   const int run = lb / nchunks, ch = lb - run * nchunks;
-  if (!conv[run]) return;
+  if (conv[run] != 1) return;   // 2 marks a narrowing, handled by k_narrow
   const int64_t chunk = (N + nchunks - 1) / nchunks;
   const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
   for (int64_t n = lo + threadIdx.x; n < hi; n += 256) {
@@ -804,7 +804,7 @@ void configure_solve(BicgSolve& b, const cbs_params* prm) {
   b.ru_factor = 1e-2;
   b.narrow_tol = b.mixed ? std::max(prm->inner_tol, prm->tol) : 0.0;
   b.max_iter = prm->max_iter;
-  b.max_ru = b.mixed ? std::max(prm->max_refine, 1) : (1 << 30);
+  b.max_ru = std::max(prm->max_refine, 1);
   b.half_stop = prm->half_stop;
 }
 

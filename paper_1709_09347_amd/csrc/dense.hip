@@ -312,11 +312,15 @@ __global__ void __launch_bounds__(SWG) k_jacobi_svd(int32_t n, c64* A, int32_t l
     sigma[512 + j] = sqrt(s2);   // scratch area after the output
   }
   __syncthreads();
+  // ranks under a strict total order (a non-finite norm counts as -1, ties by index), so
+  // perm is a permutation of 0..n-1 whatever the values are
   for (int j = tid; j < n; j += SWG) {
-    const double sj = sigma[512 + j];
+    const double sj0 = sigma[512 + j];
+    const double sj = isfinite(sj0) ? sj0 : -1.0;
     int rank = 0;
     for (int k = 0; k < n; ++k) {
-      const double sk = sigma[512 + k];
+      const double sk0 = sigma[512 + k];
+      const double sk = isfinite(sk0) ? sk0 : -1.0;
       rank += (sk > sj || (sk == sj && k < j)) ? 1 : 0;
     }
     perm[rank] = j;

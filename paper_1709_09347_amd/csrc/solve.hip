@@ -275,6 +275,11 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
   std::vector<double> hsig(n);
   CBS_HIP(hipMemcpyAsync(hsig.data(), sig, n * sizeof(double), hipMemcpyDeviceToHost, st));
   CBS_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(hsig[i])) {
+      set_error("non-finite singular values of the Hankel matrix (a linear solve diverged)");
+      return CBS_ENONFINITE;
+    }
   int m = 0;
   for (int i = 0; i < n; ++i)
     if (hsig[i] > prm->delta * hsig[0]) ++m;

@@ -303,6 +303,7 @@ const char* cbs_strerror(int32_t code) {
     case CBS_EBREAKDOWN: return "BiCG breakdown";
     case CBS_ERANK: return "Hankel rank saturated (subspace too small)";
     case CBS_ETOOMANY: return "more eigenvalues than the output holds";
+    case CBS_ENONFINITE: return "non-finite moments";
     default: return "unknown error";
   }
 }
