@@ -248,6 +248,45 @@ __device__ __forceinline__ void sum_part(const double* part, int64_t off, int n,
 }
 
 __device__ __forceinline__ bool is_active(int st) { return st == ST_ACT_LO || st == ST_ACT_HI; }
+
+// Compact lists of the active runs of each phase (ascending) and their counts, so the
+// iteration kernels launch over full groups of active runs.  One block of 256 threads.
+__device__ void build_lists(BicgScal& sc, int32_t nruns) {
+  __shared__ int wcnt[2][4];
+  __shared__ int base[2];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) base[0] = base[1] = 0;
+  __syncthreads();
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r0 = 0; r0 < nruns; r0 += 256) {
+    const int run = r0 + tid;
+    const int st = (run < nruns) ? sc.status[run] : -1;
+    const bool lo = st == ST_ACT_LO, hi = st == ST_ACT_HI;
+    const unsigned long long mlo = __ballot(lo), mhi = __ballot(hi);
+    if (lane == 0) {
+      wcnt[0][wv] = __popcll(mlo);
+      wcnt[1][wv] = __popcll(mhi);
+    }
+    __syncthreads();
+    int olo = base[0], ohi = base[1];
+    for (int w = 0; w < wv; ++w) {
+      olo += wcnt[0][w];
+      ohi += wcnt[1][w];
+    }
+    if (lo) sc.list[olo + __popcll(mlo & below)] = run;
+    if (hi) sc.list[nruns + ohi + __popcll(mhi & below)] = run;
+    __syncthreads();
+    if (tid == 0) {
+      base[0] += wcnt[0][0] + wcnt[0][1] + wcnt[0][2] + wcnt[0][3];
+      base[1] += wcnt[1][0] + wcnt[1][1] + wcnt[1][2] + wcnt[1][3];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    sc.n_active[0] = base[0];
+    sc.n_active[1] = base[1];
+  }
+}
 __device__ __forceinline__ bool is_ru(int st) { return st == ST_RU_LO || st == ST_RU_HI; }
 
 __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
@@ -266,12 +305,15 @@ __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t 
     sc.brk[run] = 0;
     sc.halt[run] = 0;
     sc.conv[run] = 0;
+    sc.ru_it[run] = 0;
     sc.ru_thr[run] = 0.0;
     const bool zero = !(s[2] > 0);
     sc.relres[2 * run] = zero ? 0.0 : 1.0;
     sc.relres[2 * run + 1] = zero ? 0.0 : 1.0;
     sc.status[run] = zero ? ST_DONE : start;
   }
+  __syncthreads();
+  build_lists(sc, nruns);
 }
 
 __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t n_atoms, const double2* sig_lo,
@@ -307,7 +349,8 @@ __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t 
 }
 
 __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
-                                            double tol, int32_t max_iter, double narrow_tol, double ru_factor) {
+                                            double tol, int32_t max_iter, double narrow_tol, double ru_factor,
+                                            int32_t lo_window) {
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
     const int st = sc.status[run];
     if (!is_active(st)) continue;
@@ -327,12 +370,14 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
     sc.beta[run] = bad ? make_double2(0, 0) : cdiv<double>(rn, ro);
     sc.rho_prev[run] = ro;
     sc.rho[run] = rn;
-    if (conv || bad || it >= max_iter || fmax(rr, rrt) < sc.ru_thr[run]) {
+    const bool stalled = (st == ST_ACT_LO) && (it - sc.ru_it[run] >= lo_window);
+    if (conv || bad || it >= max_iter || fmax(rr, rrt) < sc.ru_thr[run] || stalled) {
       sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
     } else if (st == ST_ACT_HI && narrow_tol > 0.0 && sc.ru_thr[run] >= 0.0 && fmax(rr, rrt) < narrow_tol) {
       // the residual is small enough for complex64 vectors and operator applications
       sc.status[run] = ST_ACT_LO;
       sc.conv[run] = 2;
+      sc.ru_it[run] = it;
       sc.ru_thr[run] = fmax(rr, rrt) * ru_factor;
     }
   }
@@ -340,8 +385,6 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
 
 __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
                                             double tol, int32_t max_iter, int32_t max_ru, double ru_factor) {
-  __shared__ int cnt[2][4];
-  int act_lo = 0, act_hi = 0;
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
     int st = sc.status[run];
     if (is_ru(st)) {
@@ -353,6 +396,7 @@ __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t 
       sc.relres[2 * run + 1] = rrt;
       const int nru = sc.nru[run] + 1;
       sc.nru[run] = nru;
+      sc.ru_it[run] = sc.iters[run];
       sc.xcoef[run] = make_double2(0, 0);
       const double2 rn = make_double2(s[0], s[1]);
       if (rr < tol && rrt < tol) {
@@ -383,20 +427,9 @@ __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t 
       }
       sc.status[run] = st;
     }
-    act_lo += (st == ST_ACT_LO) ? 1 : 0;
-    act_hi += (st == ST_ACT_HI) ? 1 : 0;
-  }
-  act_lo = (int)wsum<double>((double)act_lo);
-  act_hi = (int)wsum<double>((double)act_hi);
-  if ((threadIdx.x & 63) == 0) {
-    cnt[0][threadIdx.x >> 6] = act_lo;
-    cnt[1][threadIdx.x >> 6] = act_hi;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    sc.n_active[0] = cnt[0][0] + cnt[0][1] + cnt[0][2] + cnt[0][3];
-    sc.n_active[1] = cnt[1][0] + cnt[1][1] + cnt[1][2] + cnt[1][3];
-  }
+  build_lists(sc, nruns);
 }
 
 __global__ void k_clear_conv(BicgScal sc, int32_t nruns) {
@@ -472,6 +505,8 @@ int32_t bicg_alloc(BicgSolve& b, const char* tag) {
   CBS_TRY(ws_get(ws, (t + ".nru").c_str(), R, &b.sc.nru));
   CBS_TRY(ws_get(ws, (t + ".conv").c_str(), R, &b.sc.conv));
   CBS_TRY(ws_get(ws, (t + ".nact").c_str(), 2, &b.sc.n_active));
+  CBS_TRY(ws_get(ws, (t + ".ruit").c_str(), R, &b.sc.ru_it));
+  CBS_TRY(ws_get(ws, (t + ".list").c_str(), 2 * R, &b.sc.list));
   return CBS_OK;
 }
 
@@ -508,11 +543,15 @@ static int32_t enqueue_stencil_bra(BicgSolve& b, BicgVecs<T>& v, int32_t need, i
   l.status = b.sc.status;
   l.need_status = need;
   l.sig_part = v.sig;
+  const int ph = (need == ST_ACT_LO) ? 0 : 1;
+  l.list = b.sc.list + (size_t)ph * b.nruns;
+  l.count = b.sc.n_active + ph;
   if (v.ev0) CBS_HIP(hipEventRecord(v.ev0, st));
   CBS_TRY(launch_stencil<T>(s, true, l, v.tile_y, st));
   if (v.ev1) CBS_HIP(hipEventRecord(v.ev1, st));
   if (s->proj.n_atoms > 0)
-    CBS_TRY(launch_bra<T>(s, b.nruns, v.Pb[parity & 1], b.coef, b.sc.status, need, v.KT, b.signl, st, true));
+    CBS_TRY(launch_bra<T>(s, b.nruns, v.Pb[parity & 1], b.coef, b.sc.status, need, v.KT, b.signl, st, true,
+                          l.list, l.count));
   return CBS_OK;
 }
 
@@ -527,11 +566,11 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
   CBS_HIP(hipGetLastError());
   if (b.mixed)
     CBS_TRY(launch_update<float>(s, b.nruns, b.lo.R, b.lo.Q, b.lo.KT, b.sc.alpha, b.sc.status, ST_ACT_LO,
-                                 b.upd_part, b.nchunks, st));
+                                 b.upd_part, b.nchunks, st, b.sc.list, b.sc.n_active));
   CBS_TRY(launch_update<double>(s, b.nruns, b.hi.R, b.hi.Q, b.hi.KT, b.sc.alpha, b.sc.status, ST_ACT_HI,
-                                b.upd_part, b.nchunks, st));
+                                b.upd_part, b.nchunks, st, b.sc.list + b.nruns, b.sc.n_active + 1));
   hipLaunchKernelGGL(k_s2, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.upd_part, b.tol,
-                     b.max_iter, b.narrow_tol, b.ru_factor);
+                     b.max_iter, b.narrow_tol, b.ru_factor, b.lo_window);
   CBS_HIP(hipGetLastError());
   if (b.half_stop && b.n_q > 0) {
     hipLaunchKernelGGL(k_half_stop, dim3(1), dim3(256), 0, st, b.sc, b.nruns / (b.n_q * b.L), b.n_q, b.L);

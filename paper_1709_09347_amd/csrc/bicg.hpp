@@ -37,7 +37,9 @@ struct BicgScal {
   int32_t* halt;
   int32_t* nru;
   int32_t* conv;      // phase change this iteration: 1 widen to complex128, 2 narrow to complex64
+  int32_t* ru_it;     // iteration of the last replacement (complex64 stagnation guard)
   int32_t* n_active;  // [2]: active runs in the complex64 / complex128 phase
+  int32_t* list;      // [2][nruns]: the active runs of each phase, ascending (n_active entries)
 };
 
 // Vectors of one precision (pairs: primal, dual per point, run-major).
@@ -73,6 +75,7 @@ struct BicgSolve {
   BicgScal sc{};
   double tol = 1e-10, ru_factor = 1e-2, narrow_tol = 0.0;
   int32_t max_iter = 10000, max_ru = 1000, half_stop = 0;
+  int32_t lo_window = 300;   // complex64 iterations without a 100x drop before a forced replacement
 };
 
 struct NodeSolve {

@@ -96,6 +96,17 @@ __device__ __forceinline__ int mfma16_row(int lane, int v) {
 // multiple of 8.
 __device__ __forceinline__ int xcd_remap(int bid, int nb) { return (bid & 7) * (nb >> 3) + (bid >> 3); }
 
+// Logical block of a launch whose first nl logical blocks carry work (nl may be below the
+// grid when the work comes from a device-side count of active runs): the nl blocks are
+// spread over the 8 XCDs (hardware block b runs on XCD b % 8) so that consecutive logical
+// blocks share one XCD; -1 for blocks without work.
+__device__ __forceinline__ int remap_active(int bid, int nl) {
+  const int per = (nl + 7) >> 3;
+  if ((bid >> 3) >= per) return -1;
+  const int lb = (bid & 7) * per + (bid >> 3);
+  return (lb < nl) ? lb : -1;
+}
+
 template <typename R>
 __device__ __forceinline__ R wsum(R v) {
 #pragma unroll
@@ -232,6 +243,8 @@ struct StencilLaunch {
   const int32_t* status;    // [nruns] or NULL (no filter)
   int32_t need_status;      // blocks of runs whose status differs return at once
   double2* sig_part;        // BiCG [nruns*ntiles]
+  const int32_t* list;      // device [nruns] active runs (ascending) or NULL: all runs
+  const int32_t* count;     // device: entries of list (with list)
 };
 template <typename R>
 int32_t launch_stencil(const cbs_system* s, bool bicg, const StencilLaunch& a, int32_t tile_y,
@@ -245,13 +258,15 @@ int32_t autotune_tiles(cbs_system* s, hipStream_t st);
 template <typename R>
 int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunCoef* coef,
                    const int32_t* status, int32_t need_status, void* kt, double2* signl,
-                   hipStream_t st, bool phased);
+                   hipStream_t st, bool phased, const int32_t* list = nullptr,
+                   const int32_t* count = nullptr);
 
 // Fused pointwise kernels.
 template <typename R>
 int32_t launch_update(const cbs_system* s, int32_t nruns, void* r, const void* q, const void* kt,
                       const double2* alpha, const int32_t* status, int32_t need_status, double* part,
-                      int32_t nchunks, hipStream_t st);
+                      int32_t nchunks, hipStream_t st, const int32_t* list = nullptr,
+                      const int32_t* count = nullptr);
 template <typename R>
 int32_t launch_ket_add(const cbs_system* s, int32_t nruns, void* q, const void* kt, hipStream_t st);
 

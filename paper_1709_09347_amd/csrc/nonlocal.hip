@@ -34,6 +34,8 @@ struct BraArgs {
   const int32_t* status;
   Pair<R>* kt;         // [run][atom][3][4]
   double2* signl;      // [run][atom] or NULL
+  const int32_t* list;    // MFMA bra: active runs (ascending) or NULL
+  const int32_t* count;   // device count of list entries
 };
 
 template <typename R>
@@ -134,15 +136,25 @@ __device__ __forceinline__ mf4<float>::T mfma16x16x4(float a, float b, mf4<float
 template <typename R>
 __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
   __shared__ cplx<R> cs[16][2][4];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  if (lb >= a.nlogical) return;
+  __shared__ int srun[16];
+  // slots: the runs themselves, or the entries of the active-run list
+  const int nslots = (a.list != nullptr) ? *a.count : a.nruns;
+  const int nl = min(a.nlogical, ((nslots + 15) / 16) * a.n_atoms);
+  const int lb = remap_active(blockIdx.x, nl);
+  if (lb < 0) return;
   const int chunk = lb / a.n_atoms;
   const int atom = lb - chunk * a.n_atoms;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   int any = 0;
   if (tid < 16) {
-    const int run = chunk * 16 + tid;
-    any = (run < a.nruns) && (a.status == nullptr || a.status[run] == a.need_status);
+    const int slot = chunk * 16 + tid;
+    int run = -1;
+    if (slot < nslots) {
+      run = (a.list != nullptr) ? a.list[slot] : slot;
+      if (a.status != nullptr && a.status[run] != a.need_status) run = -1;
+    }
+    srun[tid] = run;
+    any = run >= 0;
   }
   if (!__syncthreads_or(any)) return;
   // Every wave covers all 16 runs (four groups g of 4 runs: four independent MFMA chains
@@ -156,8 +168,8 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
   bool rvalid[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
-    const int run = chunk * 16 + 4 * g + (row >> 2);
-    rvalid[g] = (run < a.nruns) && (a.status == nullptr || a.status[run] == a.need_status);
+    const int run = srun[4 * g + (row >> 2)];
+    rvalid[g] = run >= 0;
     zp[g] = rvalid[g] ? ccast<R, double>(a.coef[run].c[3 * half + 1]) : mkc<R>(0, 0);
     zm[g] = rvalid[g] ? ccast<R, double>(a.coef[run].c[3 * half + 2]) : mkc<R>(0, 0);
     vrow[g] = reinterpret_cast<const cplx<R>*>(a.v + (int64_t)(rvalid[g] ? run : 0) * a.N) + half;
@@ -207,8 +219,8 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
   for (int t = tid; t < 16 * 24; t += 256) {
     const int r2 = t / 24, rem = t - r2 * 24;
     const int h2 = rem & 1, i = (rem >> 1) & 3, sw = rem >> 3;
-    const int rr = chunk * 16 + r2;
-    if (rr >= a.nruns || (a.status != nullptr && a.status[rr] != a.need_status)) continue;
+    const int rr = srun[r2];
+    if (rr < 0) continue;
     const RunCoef& cf = cfp[rr];
     // K[w][i] = h z^-w c: w = -1 -> cp, 0 -> c0, +1 -> cm
     const cplx<R> f = ccast<R, double>(cf.c[3 * h2 + (sw == 0 ? 1 : sw == 1 ? 0 : 2)]);
@@ -217,8 +229,8 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
     dst[h2] = k;
   }
   if (a.signl != nullptr && tid < 16) {
-    const int rr = chunk * 16 + tid;
-    if (rr < a.nruns && (a.status == nullptr || a.status[rr] == a.need_status)) {
+    const int rr = srun[tid];
+    if (rr >= 0) {
       double2 sg = make_double2(0.0, 0.0);
       for (int i = 0; i < 4; ++i) {
         const cplx<R> t = cscale<R>(cmulc<R>(cs[tid][1][i], cs[tid][0][i]), a.coeff[4 * atom + i]);
@@ -238,7 +250,7 @@ static bool bra_plain() {
 template <typename R>
 int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunCoef* coef,
                    const int32_t* status, int32_t need_status, void* kt, double2* signl,
-                   hipStream_t st, bool phased) {
+                   hipStream_t st, bool phased, const int32_t* list, const int32_t* count) {
   const Projector& pr = s->proj;
   if (pr.n_atoms == 0 || nruns <= 0) return CBS_OK;
   BraArgs<R> a;
@@ -256,7 +268,15 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
   a.status = status;
   a.kt = (Pair<R>*)kt;
   a.signl = signl;
+  a.list = nullptr;   // the plain bra filters by status
+  a.count = nullptr;
+  if ((list == nullptr) != (count == nullptr)) {
+    set_error("launch_bra: a run list needs its count");
+    return CBS_EINVAL;
+  }
   if (phased && !bra_plain()) {
+    a.list = list;
+    a.count = count;
     a.nlogical = ((nruns + 15) / 16) * pr.n_atoms;
     const int grid = (a.nlogical + 7) / 8 * 8;
     hipLaunchKernelGGL(k_bra_mfma<R>, dim3(grid), dim3(256), 0, st, a);
@@ -284,6 +304,8 @@ struct UpdArgs {
   const double2* alpha;
   const int32_t* status;
   double* part;   // [run][chunk][4]
+  const int32_t* list;    // active runs (ascending) or NULL
+  const int32_t* count;   // device count of list entries
 };
 
 // One workgroup updates UB consecutive runs over a chunk of points: each point's
@@ -293,16 +315,24 @@ constexpr int UB = 4;
 template <typename R>
 __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
   __shared__ double red[4][UB][4];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  if (lb >= a.nlogical) return;
+  const int nslots = (a.list != nullptr) ? *a.count : a.nruns;
+  const int nl = min(a.nlogical, ((nslots + UB - 1) / UB) * a.nchunks);
+  const int lb = remap_active(blockIdx.x, nl);
+  if (lb < 0) return;
   const int rc = lb / a.nchunks;
   const int ch = lb - rc * a.nchunks;
-  const int r0 = rc * UB;
+  int run[UB];
   bool act[UB];
   bool any = false;
 #pragma unroll
   for (int k = 0; k < UB; ++k) {
-    act[k] = (r0 + k < a.nruns) && (a.status[r0 + k] == a.need_status);
+    const int slot = rc * UB + k;
+    run[k] = 0;
+    act[k] = false;
+    if (slot < nslots) {
+      run[k] = (a.list != nullptr) ? a.list[slot] : slot;
+      act[k] = a.status[run[k]] == a.need_status;
+    }
     any = any || act[k];
   }
   if (!any) return;
@@ -310,7 +340,7 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
   cplx<R> aa[UB];
 #pragma unroll
   for (int k = 0; k < UB; ++k) {
-    const double2 al = act[k] ? a.alpha[r0 + k] : make_double2(0, 0);
+    const double2 al = act[k] ? a.alpha[run[k]] : make_double2(0, 0);
     aa[k] = mkc<R>((R)al.x, (R)al.y);
   }
   const int64_t lo = ch * a.chunk;
@@ -335,7 +365,7 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
 #pragma unroll
         for (int k = 0; k < UB; ++k) {
           if (!act[k]) continue;
-          const Pair<R>* kt = a.kt + (int64_t)(r0 + k) * a.n_atoms * 12 + off;
+          const Pair<R>* kt = a.kt + (int64_t)run[k] * a.n_atoms * 12 + off;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const Pair<R> kk = kt[i];
@@ -348,7 +378,7 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
 #pragma unroll
     for (int k = 0; k < UB; ++k) {
       if (!act[k]) continue;
-      const int64_t g = (int64_t)(r0 + k) * a.N + n;
+      const int64_t g = (int64_t)run[k] * a.N + n;
       Pair<R> q = a.q[g];
       q.a = cadd<R>(q.a, kq[k].a);
       q.b = cadd<R>(q.b, kq[k].b);
@@ -374,7 +404,7 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
   if (tid < 4 * UB) {
     const int k = tid >> 2, j = tid & 3;
     if (act[k])
-      a.part[((int64_t)(r0 + k) * a.nchunks + ch) * 4 + j] = red[0][k][j] + red[1][k][j] + red[2][k][j] + red[3][k][j];
+      a.part[((int64_t)run[k] * a.nchunks + ch) * 4 + j] = red[0][k][j] + red[1][k][j] + red[2][k][j] + red[3][k][j];
   }
 }
 
@@ -386,7 +416,11 @@ int32_t update_chunks(const cbs_system* s) {
 template <typename R>
 int32_t launch_update(const cbs_system* s, int32_t nruns, void* r, const void* q, const void* kt,
                       const double2* alpha, const int32_t* status, int32_t need_status, double* part,
-                      int32_t nchunks, hipStream_t st) {
+                      int32_t nchunks, hipStream_t st, const int32_t* list, const int32_t* count) {
+  if ((list == nullptr) != (count == nullptr)) {
+    set_error("launch_update: a run list needs its count");
+    return CBS_EINVAL;
+  }
   if (nruns <= 0) return CBS_OK;
   UpdArgs<R> a;
   a.need_status = need_status;
@@ -405,6 +439,8 @@ int32_t launch_update(const cbs_system* s, int32_t nruns, void* r, const void* q
   a.alpha = alpha;
   a.status = status;
   a.part = part;
+  a.list = list;
+  a.count = count;
   const int grid = (a.nlogical + 7) / 8 * 8;
   hipLaunchKernelGGL(k_update<R>, dim3(grid), dim3(256), 0, st, a);
   CBS_HIP(hipGetLastError());
@@ -492,10 +528,11 @@ int32_t launch_from_pairs(int64_t N, int32_t nvec, const void* pairs, void* y, h
 
 #define INST(R)                                                                                   \
   template int32_t launch_bra<R>(const cbs_system*, int32_t, const void*, const RunCoef*,         \
-                                 const int32_t*, int32_t, void*, double2*, hipStream_t, bool);    \
+                                 const int32_t*, int32_t, void*, double2*, hipStream_t, bool,     \
+                                 const int32_t*, const int32_t*);                                 \
   template int32_t launch_update<R>(const cbs_system*, int32_t, void*, const void*, const void*,  \
                                     const double2*, const int32_t*, int32_t, double*, int32_t,    \
-                                    hipStream_t);                                                 \
+                                    hipStream_t, const int32_t*, const int32_t*);                 \
   template int32_t launch_ket_add<R>(const cbs_system*, int32_t, void*, const void*, hipStream_t); \
   template int32_t launch_to_pairs<R>(int64_t, int32_t, const void*, void*, hipStream_t);         \
   template int32_t launch_from_pairs<R>(int64_t, int32_t, const void*, void*, hipStream_t);

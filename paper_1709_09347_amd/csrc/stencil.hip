@@ -39,6 +39,8 @@ struct StArgs {
   const int32_t* status;
   int32_t need_status;
   double2* sig_part;
+  const int32_t* list;    // active runs (ascending) or NULL
+  const int32_t* count;   // device count of list entries
 };
 
 __device__ __forceinline__ double2 wave_sum2(double2 v) {
@@ -56,12 +58,12 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
   __shared__ double2 red[8];
   Pair<R>* lds = reinterpret_cast<Pair<R>*>(smem_raw);
 
-  const int nb = gridDim.x;
-  const int bid = blockIdx.x;
-  const int lb = (bid & 7) * (nb >> 3) + (bid >> 3);
-  if (lb >= a.nlogical) return;
-  const int run = lb / a.ntiles;
-  const int tile = lb - run * a.ntiles;
+  const int nl = (a.list != nullptr) ? min(a.nlogical, *a.count * a.ntiles) : a.nlogical;
+  const int lb = remap_active(blockIdx.x, nl);
+  if (lb < 0) return;
+  const int slot = lb / a.ntiles;
+  const int tile = lb - slot * a.ntiles;
+  const int run = (a.list != nullptr) ? a.list[slot] : slot;
   if (a.status != nullptr && a.status[run] != a.need_status) return;
 
   const int nx = a.nx, ny = a.ny, nz = a.nz, TY = a.ty;
@@ -299,6 +301,12 @@ int32_t launch_stencil(const cbs_system* s, bool bicg, const StencilLaunch& l, i
   a.status = l.status;
   a.need_status = l.need_status;
   a.sig_part = l.sig_part;
+  a.list = l.list;
+  a.count = l.count;
+  if ((a.list == nullptr) != (a.count == nullptr)) {
+    set_error("launch_stencil: a run list needs its count");
+    return CBS_EINVAL;
+  }
   switch (s->p) {
     case 1: return bicg ? launch_p<R, 1, true>(s, a, st) : launch_p<R, 1, false>(s, a, st);
     case 2: return bicg ? launch_p<R, 2, true>(s, a, st) : launch_p<R, 2, false>(s, a, st);
