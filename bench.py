@@ -76,6 +76,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", choices=("both", "fp64", "mixed"), default="both",
                     help="time one precision only (profiling); the JSON line needs both")
+    ap.add_argument("--iters-cap", type=int, default=0,
+                    help="cap BiCG at this many iterations (short runs for counter collection; "
+                         "no JSON line)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (the reference dispatch for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the path shards by quadrature node and "
@@ -84,6 +90,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copied 5 x 1 GiB (read 1 GiB + write 1 GiB per dispatch)", flush=True)
+        return
 
     import paper_1709_09347_amd as cbs
     import workloads as W
@@ -104,6 +119,8 @@ def main():
             if args.legs in ("both", n)]
     for name, prec in legs:
         prm = cbs.default_params(n_rhs=L, n_mom=M, precision=prec)
+        if args.iters_cap > 0:
+            prm.max_iter = args.iters_cap
         for _ in range(args.warmup):
             s.solve(E, V, prm, want_vectors=False)
         torch.cuda.synchronize()
@@ -118,7 +135,7 @@ def main():
               f"{info.max_solve_resid:.2e}, max eigen residual {info.max_eig_resid:.2e}, rc {rc}",
               file=sys.stderr, flush=True)
 
-    if args.legs != "both":
+    if args.legs != "both" or args.iters_cap > 0:
         return
     # dominant kernel: the mixed path's BiCG stencil, timed per launch (diagnostic solve)
     roof = {}

@@ -25,7 +25,8 @@
 // replacement is triggered whenever the recursive residual has dropped by `ru_factor`
 // since the last one: the FP64 iterative refinement that keeps the gap between the
 // single-precision recursive residual and the true residual below the tolerance.  A run
-// whose true residual stops falling in complex64 is widened back to complex128.  FP64
+// whose true residual stops falling in complex64 restarts in complex128.  The complex64
+// phase stores complex64 but computes in FP64 (CBS_LO_ARITH=32: FP32).  FP64
 // mode stays in the complex128 phase, where S2 only marks runs whose recursive residual
 // met tol.
 // The iteration is captured once into a HIP graph of `chunk` iterations and replayed
@@ -33,6 +34,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -182,23 +184,21 @@ __global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int
   if (tid < 4) part[((int64_t)run * nchunks + ch) * 4 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
-// Widen the search direction of runs that went back to complex128 this iteration (conv == 1).
+// Runs that went back to complex128 this iteration (conv == 1) restart from their
+// replaced residual: the old complex128 direction is cleared (beta is 0, and a stale
+// value must not turn 0 * p into NaN).
 __global__ void __launch_bounds__(256) k_widen(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* conv,
-                                               const Pair<float>* Plo, Pair<double>* Phi) {
+                                               Pair<double>* Phi) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   if (lb >= nlogical) return;
   const int run = lb / nchunks, ch = lb - run * nchunks;
   if (conv[run] != 1) return;   // 2 marks a narrowing, handled by k_narrow
   const int64_t chunk = (N + nchunks - 1) / nchunks;
   const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
-  for (int64_t n = lo + threadIdx.x; n < hi; n += 256) {
-    const int64_t g = (int64_t)run * N + n;
-    const Pair<float> p = Plo[g];
-    Pair<double> d;
-    d.a = ccast<double, float>(p.a);
-    d.b = ccast<double, float>(p.b);
-    Phi[g] = d;
-  }
+  Pair<double> z;
+  z.a = make_double2(0, 0);
+  z.b = z.a;
+  for (int64_t n = lo + threadIdx.x; n < hi; n += 256) Phi[(int64_t)run * N + n] = z;
 }
 
 // Narrow the runs that entered the complex64 phase this iteration (conv == 2): r and
@@ -412,11 +412,13 @@ __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t 
         sc.rho[run] = rn;
         const double tr = fmax(rr, rrt);
         if (st == ST_RU_LO && tr > 0.5 * sc.ru_thr[run] / ru_factor) {
-          // the complex64 recurrence stopped reducing the true residual: finish in
-          // complex128 (the replaced residual is in R64, the search direction is widened)
+          // the complex64 recurrence stopped reducing the true residual: restart BiCG in
+          // complex128 from the accumulated solution (the replaced residual is in R64,
+          // beta = 0 makes the true residual the first search direction)
           st = ST_ACT_HI;
           sc.conv[run] = 1;
           sc.ru_thr[run] = -1.0;
+          sc.beta[run] = make_double2(0, 0);
         } else if (st == ST_RU_LO) {
           st = ST_ACT_LO;
           sc.ru_thr[run] = tr * ru_factor;
@@ -612,7 +614,7 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
   CBS_HIP(hipGetLastError());
   if (b.mixed) {
     hipLaunchKernelGGL(k_widen, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, (const int32_t*)b.sc.conv,
-                       (const Pair<float>*)b.lo.Pb[parity & 1], b.hi.Pb[parity & 1]);
+                       b.hi.Pb[parity & 1]);
     hipLaunchKernelGGL(k_narrow, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, (const int32_t*)b.sc.conv,
                        (const Pair<double>*)b.hi.R, (const Pair<double>*)b.hi.Pb[parity & 1], b.hi.X, b.lo.R,
                        b.lo.Pb[parity & 1], b.lo.X, b.Y);
@@ -787,6 +789,23 @@ int32_t bicg_collect(BicgSolve& b, NodeSolve& out, hipStream_t st) {
   CBS_HIP(hipStreamSynchronize(st));
   out.n_ru = 0;
   for (int v : nru) out.n_ru = std::max(out.n_ru, v);
+  const char* verbose = getenv("CBS_VERBOSE");
+  if (verbose && verbose[0] == '1') {
+    // diagnostics: final states, iteration spread, the slowest runs
+    int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int v : out.status) cnt[(v >= 0 && v < 8) ? v : 0] += 1;
+    std::vector<int> order(b.nruns);
+    for (int r = 0; r < b.nruns; ++r) order[r] = r;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return out.iters[x] < out.iters[y]; });
+    fprintf(stderr, "[cbs] %d runs: done %d noconv %d breakdown %d halted %d; iters min %d median %d max %d\n",
+            b.nruns, cnt[ST_DONE], cnt[ST_NOCONV], cnt[ST_BREAKDOWN], cnt[ST_HALTED], out.iters[order[0]],
+            out.iters[order[b.nruns / 2]], out.iters[order[b.nruns - 1]]);
+    for (int k = std::max(0, b.nruns - 5); k < b.nruns; ++k) {
+      const int r = order[k];
+      fprintf(stderr, "[cbs]   run %d: status %d iters %d replacements %d relres %.2e %.2e\n", r, out.status[r],
+              out.iters[r], nru[r], out.relres[2 * r], out.relres[2 * r + 1]);
+    }
+  }
   out.Y = b.Y;
   // the stencil of the phase that did most of the work
   if (b.mixed) {

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <cstdio>
 #include <map>
 #include <string>
@@ -70,6 +71,14 @@ struct alignas(2 * sizeof(cplx<R>)) Pair {
   cplx<R> b;  // dual
 };
 
+template <typename Ro, typename Ri>
+__host__ __device__ __forceinline__ Pair<Ro> pcast(const Pair<Ri>& p) {
+  Pair<Ro> o;
+  o.a = ccast<Ro, Ri>(p.a);
+  o.b = ccast<Ro, Ri>(p.b);
+  return o;
+}
+
 // Coefficient triple of one vector: y = c0 (H0-E) x + cp H+ x + cm H- x.
 // Per run: [primal c0, cp, cm, dual c0, cp, cm] as complex doubles.
 struct RunCoef {
@@ -94,6 +103,22 @@ __device__ __forceinline__ int mfma16_row(int lane, int v) {
 // Remap a block id so that consecutive logical blocks run on one XCD (the
 // dispatcher hands blocks to the 8 XCDs round-robin); gridDim must be a
 // multiple of 8.
+// Address space for data read at wave-uniform addresses (the compiler then uses scalar
+// loads); the host pass of the same source has no address spaces.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CBS_CONST_AS __attribute__((address_space(4)))
+#else
+#define CBS_CONST_AS
+#endif
+
+// Arithmetic precision of the complex64-storage kernels: FP64 by default (the HBM traffic
+// halves while the operator is applied as accurately as the rounding of its complex64
+// input and output allows); CBS_LO_ARITH=32 selects FP32 arithmetic.
+inline bool lo_arith_fp32() {
+  const char* e = getenv("CBS_LO_ARITH");
+  return e && e[0] == '3' && e[1] == '2';
+}
+
 __device__ __forceinline__ int xcd_remap(int bid, int nb) { return (bid & 7) * (nb >> 3) + (bid >> 3); }
 
 // Logical block of a launch whose first nl logical blocks carry work (nl may be below the
@@ -196,7 +221,16 @@ struct Projector {
   double* pt_u64 = nullptr;      // [nnz*4]
   float* pt_u32 = nullptr;
   int32_t max_atom_entries = 0;
+  // grouped ket tables: points in groups of KG consecutive indices; group g uses the
+  // keys [grp_off[g], grp_off[g+1]) (atom*4 + (w+1), ascending) and for each key the
+  // values of its KG points (zero where the point is outside that ball)
+  int32_t* grp_off = nullptr;    // [ngroups+1]
+  int32_t* grp_key = nullptr;    // [nkeys]
+  double* grp_u64 = nullptr;     // [nkeys][KG][4]
+  float* grp_u32 = nullptr;
+  int64_t grp_nkeys = 0;
 };
+constexpr int KG = 64;   // points per ket group (one wavefront)
 
 struct LastSolve {
   int32_t n = 0;

@@ -36,6 +36,7 @@ struct BraArgs {
   double2* signl;      // [run][atom] or NULL
   const int32_t* list;    // MFMA bra: active runs (ascending) or NULL
   const int32_t* count;   // device count of list entries
+  int32_t spread;         // MFMA bra: 1 = consecutive blocks on different XCDs
 };
 
 template <typename R>
@@ -133,14 +134,17 @@ __device__ __forceinline__ mf4<float>::T mfma16x16x4(float a, float b, mf4<float
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <typename R>
+// R: storage precision (vectors, tables, K); C: arithmetic precision (MFMA, sums).
+template <typename R, typename C>
 __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
-  __shared__ cplx<R> cs[16][2][4];
+  __shared__ cplx<C> cs[16][2][4];
   __shared__ int srun[16];
   // slots: the runs themselves, or the entries of the active-run list
   const int nslots = (a.list != nullptr) ? *a.count : a.nruns;
   const int nl = min(a.nlogical, ((nslots + 15) / 16) * a.n_atoms);
-  const int lb = remap_active(blockIdx.x, nl);
+  // spread: all XCDs work on the same 16 runs at a time (different atoms), so the
+  // overlapping balls of neighbouring atoms are re-read from the memory-side cache
+  const int lb = a.spread ? ((int)blockIdx.x < nl ? (int)blockIdx.x : -1) : remap_active(blockIdx.x, nl);
   if (lb < 0) return;
   const int chunk = lb / a.n_atoms;
   const int atom = lb - chunk * a.n_atoms;
@@ -160,39 +164,40 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
   // Every wave covers all 16 runs (four groups g of 4 runs: four independent MFMA chains
   // that share each table load) over every 4th step of 4 ball entries; the four waves'
   // partial products are summed through LDS.
-  __shared__ R red[4][4][64][4];
+  __shared__ C red[4][4][64][4];
   const int row = lane & 15, kslot = lane >> 4, col = lane & 15;
   const int half = (row >> 1) & 1, reim = row & 1;
   const cplx<R>* vrow[4];
-  cplx<R> zp[4], zm[4];
+  cplx<C> zp[4], zm[4];
   bool rvalid[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     const int run = srun[4 * g + (row >> 2)];
     rvalid[g] = run >= 0;
-    zp[g] = rvalid[g] ? ccast<R, double>(a.coef[run].c[3 * half + 1]) : mkc<R>(0, 0);
-    zm[g] = rvalid[g] ? ccast<R, double>(a.coef[run].c[3 * half + 2]) : mkc<R>(0, 0);
+    zp[g] = rvalid[g] ? ccast<C, double>(a.coef[run].c[3 * half + 1]) : mkc<C>(0, 0);
+    zm[g] = rvalid[g] ? ccast<C, double>(a.coef[run].c[3 * half + 2]) : mkc<C>(0, 0);
     vrow[g] = reinterpret_cast<const cplx<R>*>(a.v + (int64_t)(rvalid[g] ? run : 0) * a.N) + half;
   }
   const int s0 = a.seg[4 * atom], s1 = a.seg[4 * atom + 1], s2 = a.seg[4 * atom + 2], s3 = a.seg[4 * atom + 3];
-  typename mf4<R>::T acc[4];
+  typename mf4<C>::T acc[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) acc[g] = {0, 0, 0, 0};
   for (int e0 = s0 + 4 * wv; e0 < s3; e0 += 16) {
     const int e = e0 + kslot;
     const bool ok = e < s3;
     int idx = 0;
-    R bv = 0;
+    C bv = 0;
     if (ok) {
       idx = a.idx[e];
-      if (col < 4) bv = a.u[4 * (int64_t)e + col];
+      if (col < 4) bv = (C)a.u[4 * (int64_t)e + col];
     }
-    cplx<R> vv[4];
+    cplx<C> vv[4];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) vv[g] = (ok && rvalid[g]) ? vrow[g][2 * (int64_t)idx] : mkc<R>(0, 0);
+    for (int g = 0; g < 4; ++g)
+      vv[g] = (ok && rvalid[g]) ? ccast<C, R>(vrow[g][2 * (int64_t)idx]) : mkc<C>(0, 0);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      const cplx<R> p = (e < s1) ? cmul<R>(zm[g], vv[g]) : (e < s2) ? vv[g] : cmul<R>(zp[g], vv[g]);
+      const cplx<C> p = (e < s1) ? cmul<C>(zm[g], vv[g]) : (e < s2) ? vv[g] : cmul<C>(zp[g], vv[g]);
       acc[g] = mfma16x16x4(reim ? p.y : p.x, bv, acc[g]);
     }
   }
@@ -207,9 +212,9 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
     if ((l2 & 15) < 4) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const R sum = red[0][g][l2][v] + red[1][g][l2][v] + red[2][g][l2][v] + red[3][g][l2][v];
-        const int r = mfma16_row<R>(l2, v);   // output row held by lane l2
-        R* dst = reinterpret_cast<R*>(&cs[4 * g + (r >> 2)][(r >> 1) & 1][l2 & 15]);
+        const C sum = red[0][g][l2][v] + red[1][g][l2][v] + red[2][g][l2][v] + red[3][g][l2][v];
+        const int r = mfma16_row<C>(l2, v);   // output row held by lane l2
+        C* dst = reinterpret_cast<C*>(&cs[4 * g + (r >> 2)][(r >> 1) & 1][l2 & 15]);
         dst[r & 1] = sum;
       }
     }
@@ -223,17 +228,17 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
     if (rr < 0) continue;
     const RunCoef& cf = cfp[rr];
     // K[w][i] = h z^-w c: w = -1 -> cp, 0 -> c0, +1 -> cm
-    const cplx<R> f = ccast<R, double>(cf.c[3 * h2 + (sw == 0 ? 1 : sw == 1 ? 0 : 2)]);
-    const cplx<R> k = cscale<R>(cmul<R>(f, cs[r2][h2][i]), a.coeff[4 * atom + i]);
+    const cplx<C> f = ccast<C, double>(cf.c[3 * h2 + (sw == 0 ? 1 : sw == 1 ? 0 : 2)]);
+    const cplx<C> k = cscale<C>(cmul<C>(f, cs[r2][h2][i]), (C)a.coeff[4 * atom + i]);
     cplx<R>* dst = reinterpret_cast<cplx<R>*>(&a.kt[((int64_t)rr * a.n_atoms + atom) * 12 + sw * 4 + i]);
-    dst[h2] = k;
+    dst[h2] = ccast<R, C>(k);
   }
   if (a.signl != nullptr && tid < 16) {
     const int rr = srun[tid];
     if (rr >= 0) {
       double2 sg = make_double2(0.0, 0.0);
       for (int i = 0; i < 4; ++i) {
-        const cplx<R> t = cscale<R>(cmulc<R>(cs[tid][1][i], cs[tid][0][i]), a.coeff[4 * atom + i]);
+        const cplx<C> t = cscale<C>(cmulc<C>(cs[tid][1][i], cs[tid][0][i]), (C)a.coeff[4 * atom + i]);
         sg.x += (double)t.x;
         sg.y += (double)t.y;
       }
@@ -270,6 +275,8 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
   a.signl = signl;
   a.list = nullptr;   // the plain bra filters by status
   a.count = nullptr;
+  const char* bm = getenv("CBS_BRA_MAP");
+  a.spread = !(bm && bm[0] == 'x');
   if ((list == nullptr) != (count == nullptr)) {
     set_error("launch_bra: a run list needs its count");
     return CBS_EINVAL;
@@ -279,7 +286,10 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
     a.count = count;
     a.nlogical = ((nruns + 15) / 16) * pr.n_atoms;
     const int grid = (a.nlogical + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_bra_mfma<R>, dim3(grid), dim3(256), 0, st, a);
+    if (std::is_same<R, float>::value && lo_arith_fp32())
+      hipLaunchKernelGGL((k_bra_mfma<R, float>), dim3(grid), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_bra_mfma<R, double>), dim3(grid), dim3(256), 0, st, a);
   } else {
     const int grid = (a.nlogical + 7) / 8 * 8;
     hipLaunchKernelGGL(k_bra<R>, dim3(grid), dim3(256), 0, st, a);
@@ -306,27 +316,33 @@ struct UpdArgs {
   double* part;   // [run][chunk][4]
   const int32_t* list;    // active runs (ascending) or NULL
   const int32_t* count;   // device count of list entries
+  const int32_t* grp_off;   // grouped ket tables (see Projector)
+  const int32_t* grp_key;
+  const R* grp_u;
 };
 
-// One workgroup updates UB consecutive runs over a chunk of points: each point's
-// projector entries (key, four values) are read once and reused for every run.
-constexpr int UB = 4;
+// One workgroup updates UR runs (consecutive active-list slots) over a chunk of point
+// groups; a wave takes one group of KG = 64 points at a time (lane = point).  The ket
+// walks the group's keys (atom, shift): every lane reads its four projector values for
+// the key (zero outside that ball) and the coefficients K of the key are the same for
+// all lanes (uniform loads), so no lane gathers per entry.
+constexpr int UR = 4;
 
-template <typename R>
+template <typename R, typename C>
 __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
-  __shared__ double red[4][UB][4];
+  __shared__ double red[4][UR][4];
   const int nslots = (a.list != nullptr) ? *a.count : a.nruns;
-  const int nl = min(a.nlogical, ((nslots + UB - 1) / UB) * a.nchunks);
+  const int nl = min(a.nlogical, ((nslots + UR - 1) / UR) * a.nchunks);
   const int lb = remap_active(blockIdx.x, nl);
   if (lb < 0) return;
   const int rc = lb / a.nchunks;
   const int ch = lb - rc * a.nchunks;
-  int run[UB];
-  bool act[UB];
+  int run[UR];
+  bool act[UR];
   bool any = false;
 #pragma unroll
-  for (int k = 0; k < UB; ++k) {
-    const int slot = rc * UB + k;
+  for (int k = 0; k < UR; ++k) {
+    const int slot = rc * UR + k;
     run[k] = 0;
     act[k] = false;
     if (slot < nslots) {
@@ -336,72 +352,89 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
     any = any || act[k];
   }
   if (!any) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  cplx<R> aa[UB];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+  cplx<C> aa[UR];
 #pragma unroll
-  for (int k = 0; k < UB; ++k) {
+  for (int k = 0; k < UR; ++k) {
+    run[k] = __builtin_amdgcn_readfirstlane(run[k]);
     const double2 al = act[k] ? a.alpha[run[k]] : make_double2(0, 0);
-    aa[k] = mkc<R>((R)al.x, (R)al.y);
+    aa[k] = mkc<C>((C)al.x, (C)al.y);
   }
-  const int64_t lo = ch * a.chunk;
-  const int64_t hi = (lo + a.chunk < a.N) ? lo + a.chunk : a.N;
-  double s[UB][4];
+  // the tables indexed by wave-uniform values are read through the scalar unit
+  typedef const CBS_CONST_AS int32_t* cint_p;
+  typedef const CBS_CONST_AS Pair<R>* ckt_p;
+  const cint_p goff = (cint_p)a.grp_off;
+  const cint_p gkey = (cint_p)a.grp_key;
+  const int64_t ngroups = (a.N + KG - 1) / KG;
+  const int64_t gpc = (ngroups + a.nchunks - 1) / a.nchunks;
+  const int64_t g0 = ch * gpc;
+  const int64_t g1 = (g0 + gpc < ngroups) ? g0 + gpc : ngroups;
+  const int64_t kstride = (int64_t)a.n_atoms * 12;
+  double s[UR][4];
 #pragma unroll
-  for (int k = 0; k < UB; ++k) s[k][0] = s[k][1] = s[k][2] = s[k][3] = 0;
-  for (int64_t n = lo + tid; n < hi; n += 256) {
-    Pair<R> kq[UB];
+  for (int k = 0; k < UR; ++k) s[k][0] = s[k][1] = s[k][2] = s[k][3] = 0;
+  for (int64_t g = g0 + wv; g < g1; g += 4) {
+    const int64_t n = g * KG + lane;
+    const bool ok = n < a.N;
+    Pair<C> kq[UR];
 #pragma unroll
-    for (int k = 0; k < UB; ++k) {
-      kq[k].a = mkc<R>(0, 0);
+    for (int k = 0; k < UR; ++k) {
+      kq[k].a = mkc<C>(0, 0);
       kq[k].b = kq[k].a;
     }
     if (a.kt != nullptr) {
-      const int e0 = a.pt_off[n], e1 = a.pt_off[n + 1];
+      const int e0 = goff[g], e1 = goff[g + 1];
       for (int e = e0; e < e1; ++e) {
-        const int key = a.pt_key[e];
-        const typename vec4<R>::T uu = reinterpret_cast<const typename vec4<R>::T*>(a.pt_u)[e];
-        const R us[4] = {uu.x, uu.y, uu.z, uu.w};
-        const int64_t off = (int64_t)(key >> 2) * 12 + (key & 3) * 4;
+        const int key = gkey[e];
+        const typename vec4<R>::T uu = reinterpret_cast<const typename vec4<R>::T*>(a.grp_u)[(int64_t)e * KG + lane];
+        const C us[4] = {(C)uu.x, (C)uu.y, (C)uu.z, (C)uu.w};
+        const int64_t koff = (int64_t)(key >> 2) * 12 + (key & 3) * 4;
 #pragma unroll
-        for (int k = 0; k < UB; ++k) {
+        for (int k = 0; k < UR; ++k) {
           if (!act[k]) continue;
-          const Pair<R>* kt = a.kt + (int64_t)run[k] * a.n_atoms * 12 + off;
+          const ckt_p kp = (ckt_p)a.kt + (int64_t)run[k] * kstride + koff;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const Pair<R> kk = kt[i];
-            kq[k].a = cfma_r<R>(kq[k].a, us[i], kk.a);
-            kq[k].b = cfma_r<R>(kq[k].b, us[i], kk.b);
+            const Pair<R> kr = kp[i];
+            const Pair<C> kk = pcast<C, R>(kr);
+            kq[k].a = cfma_r<C>(kq[k].a, us[i], kk.a);
+            kq[k].b = cfma_r<C>(kq[k].b, us[i], kk.b);
           }
         }
       }
     }
+    if (ok) {
 #pragma unroll
-    for (int k = 0; k < UB; ++k) {
-      if (!act[k]) continue;
-      const int64_t g = (int64_t)run[k] * a.N + n;
-      Pair<R> q = a.q[g];
-      q.a = cadd<R>(q.a, kq[k].a);
-      q.b = cadd<R>(q.b, kq[k].b);
-      Pair<R> r = a.r[g];
-      r.a = csub<R>(r.a, cmul<R>(aa[k], q.a));
-      r.b = csub<R>(r.b, cmul<R>(cconj<R>(aa[k]), q.b));
-      a.r[g] = r;
-      const cplx<R> rho = cmulc<R>(r.b, r.a);
-      s[k][0] += (double)rho.x;
-      s[k][1] += (double)rho.y;
-      s[k][2] += (double)cabs2<R>(r.a);
-      s[k][3] += (double)cabs2<R>(r.b);
+      for (int k = 0; k < UR; ++k) {
+        if (!act[k]) continue;
+        const int64_t gi = (int64_t)run[k] * a.N + n;
+        Pair<C> q = pcast<C, R>(a.q[gi]);
+        q.a = cadd<C>(q.a, kq[k].a);
+        q.b = cadd<C>(q.b, kq[k].b);
+        Pair<C> r = pcast<C, R>(a.r[gi]);
+        r.a = csub<C>(r.a, cmul<C>(aa[k], q.a));
+        r.b = csub<C>(r.b, cmul<C>(cconj<C>(aa[k]), q.b));
+        const Pair<R> rs = pcast<R, C>(r);
+        a.r[gi] = rs;
+        r = pcast<C, R>(rs);   // the dots of the stored residual
+        const cplx<C> rho = cmulc<C>(r.b, r.a);
+        s[k][0] += (double)rho.x;
+        s[k][1] += (double)rho.y;
+        s[k][2] += (double)cabs2<C>(r.a);
+        s[k][3] += (double)cabs2<C>(r.b);
+      }
     }
   }
 #pragma unroll
-  for (int k = 0; k < UB; ++k)
+  for (int k = 0; k < UR; ++k)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const double t = wsum<double>(s[k][j]);
       if (lane == 0) red[wv][k][j] = t;
     }
   __syncthreads();
-  if (tid < 4 * UB) {
+  if (tid < 4 * UR) {
     const int k = tid >> 2, j = tid & 3;
     if (act[k])
       a.part[((int64_t)run[k] * a.nchunks + ch) * 4 + j] = red[0][k][j] + red[1][k][j] + red[2][k][j] + red[3][k][j];
@@ -426,7 +459,7 @@ int32_t launch_update(const cbs_system* s, int32_t nruns, void* r, const void* q
   a.need_status = need_status;
   a.nchunks = nchunks;
   a.nruns = nruns;
-  a.nlogical = ((nruns + UB - 1) / UB) * nchunks;
+  a.nlogical = ((nruns + UR - 1) / UR) * nchunks;
   a.n_atoms = s->proj.n_atoms;
   a.N = s->N;
   a.chunk = (s->N + nchunks - 1) / nchunks;
@@ -441,8 +474,14 @@ int32_t launch_update(const cbs_system* s, int32_t nruns, void* r, const void* q
   a.part = part;
   a.list = list;
   a.count = count;
+  a.grp_off = s->proj.grp_off;
+  a.grp_key = s->proj.grp_key;
+  a.grp_u = std::is_same<R, double>::value ? (const R*)s->proj.grp_u64 : (const R*)s->proj.grp_u32;
   const int grid = (a.nlogical + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_update<R>, dim3(grid), dim3(256), 0, st, a);
+  if (std::is_same<R, float>::value && lo_arith_fp32())
+    hipLaunchKernelGGL((k_update<R, float>), dim3(grid), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_update<R, double>), dim3(grid), dim3(256), 0, st, a);
   CBS_HIP(hipGetLastError());
   return CBS_OK;
 }

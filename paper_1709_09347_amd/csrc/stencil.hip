@@ -15,6 +15,7 @@
 //    the write of p_new and the local part of sigma = pt^H q;
 //  * blocks are renumbered so that consecutive tiles of a run land on one XCD, where
 //    they share the halo rows in that XCD's L2.
+#include <cstdlib>
 #include <type_traits>
 
 #include "cbs_internal.hpp"
@@ -25,9 +26,10 @@ template <typename R>
 struct StArgs {
   int32_t nx, ny, nz, ty, ntiles, nlogical, nbuf;
   int64_t N;
-  R kin;      // -1/(2 h^2)
-  R c[5];     // c_0..c_p
-  const R* vloc;
+  double kin;   // -1/(2 h^2)
+  double c[5];  // c_0..c_p
+  const R* vloc;          // local potential in the storage precision
+  const double* vloc64;   // and in complex128 arithmetic's precision
   const Pair<R>* rin;
   const Pair<R>* pold;
   Pair<R>* pnew;
@@ -52,7 +54,8 @@ __device__ __forceinline__ double2 wave_sum2(double2 v) {
   return v;
 }
 
-template <typename R, int P, bool BICG>
+// R: storage precision of the vectors (and of the LDS plane); C: arithmetic precision.
+template <typename R, typename C, int P, bool BICG>
 __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double2 red[8];
@@ -80,43 +83,47 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
   const int y0 = tile * TY - P;
 
   const RunCoef cf = a.coef[run];
-  const cplx<R> c0a = ccast<R, double>(cf.c[0]), cpa = ccast<R, double>(cf.c[1]),
-                cma = ccast<R, double>(cf.c[2]);
-  const cplx<R> c0b = ccast<R, double>(cf.c[3]), cpb = ccast<R, double>(cf.c[4]),
-                cmb = ccast<R, double>(cf.c[5]);
-  const R Erun = (R)cf.E;
-  cplx<R> ba = mkc<R>(0, 0), bb = ba, xa = ba, xb = ba;
+  const cplx<C> c0a = ccast<C, double>(cf.c[0]), cpa = ccast<C, double>(cf.c[1]),
+                cma = ccast<C, double>(cf.c[2]);
+  const cplx<C> c0b = ccast<C, double>(cf.c[3]), cpb = ccast<C, double>(cf.c[4]),
+                cmb = ccast<C, double>(cf.c[5]);
+  const C Erun = (C)cf.E;
+  cplx<C> ba = mkc<C>(0, 0), bb = ba, xa = ba, xb = ba;
   bool do_x = false;
   if (BICG) {
     const double2 bt = a.beta[run];
-    ba = mkc<R>((R)bt.x, (R)bt.y);
-    bb = cconj<R>(ba);
+    ba = mkc<C>((C)bt.x, (C)bt.y);
+    bb = cconj<C>(ba);
     const double2 xc = a.xcoef[run];
-    xa = mkc<R>((R)xc.x, (R)xc.y);
-    xb = cconj<R>(xa);
+    xa = mkc<C>((C)xc.x, (C)xc.y);
+    xb = cconj<C>(xa);
     do_x = (xc.x != 0.0 || xc.y != 0.0);
   }
-  R zc[2 * P + 1];
+  const C kin = (C)a.kin;
+  C cc[P + 1];
 #pragma unroll
-  for (int d = 0; d <= 2 * P; ++d) zc[d] = a.kin * a.c[d > P ? d - P : P - d];
+  for (int j = 0; j <= P; ++j) cc[j] = (C)a.c[j];
+  C zc[2 * P + 1];
+#pragma unroll
+  for (int d = 0; d <= 2 * P; ++d) zc[d] = kin * cc[d > P ? d - P : P - d];
 
-  Pair<R> acc[2 * P + 1];
+  Pair<C> acc[2 * P + 1];
 #pragma unroll
   for (int d = 0; d <= 2 * P; ++d) {
-    acc[d].a = mkc<R>(0, 0);
-    acc[d].b = mkc<R>(0, 0);
+    acc[d].a = mkc<C>(0, 0);
+    acc[d].b = mkc<C>(0, 0);
   }
-  cplx<R> pdq[P + 1];
+  cplx<C> pdq[P + 1];
 #pragma unroll
-  for (int d = 0; d <= P; ++d) pdq[d] = mkc<R>(0, 0);
+  for (int d = 0; d <= P; ++d) pdq[d] = mkc<C>(0, 0);
   double2 sig = make_double2(0.0, 0.0);
 
   for (int m = -P; m < nz + P; ++m) {
     const bool real = (m >= 0) && (m < nz);
-    Pair<R> s;
-    s.a = mkc<R>(0, 0);
+    Pair<C> s;
+    s.a = mkc<C>(0, 0);
     s.b = s.a;
-    Pair<R> inb = s;
+    Pair<C> inb = s;
     if (real) {
       Pair<R>* buf = lds + ((a.nbuf == 2) ? (m & 1) * region : 0);
       if (a.nbuf == 1 && m > 0) __syncthreads();   // single buffer: previous plane fully read
@@ -127,29 +134,32 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
         int gy = uy % ny;
         if (gy < 0) gy += ny;
         const int64_t n = base + xx + (int64_t)nx * gy + plane * m;
-        Pair<R> v = a.rin[n];
         if (BICG) {
-          const Pair<R> po = a.pold[n];
-          v.a = cfma<R>(v.a, ba, po.a);
-          v.b = cfma<R>(v.b, bb, po.b);
+          Pair<C> v = pcast<C, R>(a.rin[n]);
+          const Pair<C> po = pcast<C, R>(a.pold[n]);
+          v.a = cfma<C>(v.a, ba, po.a);
+          v.b = cfma<C>(v.b, bb, po.b);
+          const Pair<R> vs = pcast<R, C>(v);   // the stored direction is the one applied
           if (r >= P && r < P + TY && uy < ny) {
-            a.pnew[n] = v;
+            a.pnew[n] = vs;
             if (do_x) {
-              Pair<R> xv = a.x[n];
-              xv.a = cfma<R>(xv.a, xa, po.a);
-              xv.b = cfma<R>(xv.b, xb, po.b);
-              a.x[n] = xv;
+              Pair<C> xv = pcast<C, R>(a.x[n]);
+              xv.a = cfma<C>(xv.a, xa, po.a);
+              xv.b = cfma<C>(xv.b, xb, po.b);
+              a.x[n] = pcast<R, C>(xv);
             }
           }
+          buf[e] = vs;
+        } else {
+          buf[e] = a.rin[n];
         }
-        buf[e] = v;
       }
       __syncthreads();
       if (own) {
         const int row = (ty + P) * nx;
-        const Pair<R> v = buf[row + tx];
-        cplx<R> sa = cscale<R>(v.a, (R)2 * a.c[0]);
-        cplx<R> sb = cscale<R>(v.b, (R)2 * a.c[0]);
+        const Pair<C> v = pcast<C, R>(buf[row + tx]);
+        cplx<C> sa = cscale<C>(v.a, (C)2 * cc[0]);
+        cplx<C> sb = cscale<C>(v.b, (C)2 * cc[0]);
 #pragma unroll
         for (int j = 1; j <= P; ++j) {
           int xl = tx - j;
@@ -162,63 +172,66 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
           xr -= (xr >= nx) ? nx : 0;
           xr -= (xr >= nx) ? nx : 0;
           xr -= (xr >= nx) ? nx : 0;
-          const Pair<R> l = buf[row + xl];
-          const Pair<R> rr = buf[row + xr];
-          const Pair<R> dn = buf[row - j * nx + tx];
-          const Pair<R> up = buf[row + j * nx + tx];
-          const R cj = a.c[j];
-          sa = cfma_r<R>(sa, cj, cadd<R>(cadd<R>(l.a, rr.a), cadd<R>(dn.a, up.a)));
-          sb = cfma_r<R>(sb, cj, cadd<R>(cadd<R>(l.b, rr.b), cadd<R>(dn.b, up.b)));
+          const Pair<C> l = pcast<C, R>(buf[row + xl]);
+          const Pair<C> rr = pcast<C, R>(buf[row + xr]);
+          const Pair<C> dn = pcast<C, R>(buf[row - j * nx + tx]);
+          const Pair<C> up = pcast<C, R>(buf[row + j * nx + tx]);
+          const C cj = cc[j];
+          sa = cfma_r<C>(sa, cj, cadd<C>(cadd<C>(l.a, rr.a), cadd<C>(dn.a, up.a)));
+          sb = cfma_r<C>(sb, cj, cadd<C>(cadd<C>(l.b, rr.b), cadd<C>(dn.b, up.b)));
         }
-        const R vd = a.vloc[tx + (int64_t)nx * y + plane * m] - Erun;
-        sa = cfma_r<R>(cscale<R>(sa, a.kin), vd, v.a);
-        sb = cfma_r<R>(cscale<R>(sb, a.kin), vd, v.b);
-        inb.a = cmul<R>(c0a, sa);
-        inb.b = cmul<R>(c0b, sb);
-        s.a = cmul<R>(c0a, v.a);
-        s.b = cmul<R>(c0b, v.b);
+        const int64_t pt = tx + (int64_t)nx * y + plane * m;
+        const C vl = (sizeof(C) == 8) ? (C)a.vloc64[pt] : (C)a.vloc[pt];
+        const C vd = vl - Erun;
+        sa = cfma_r<C>(cscale<C>(sa, kin), vd, v.a);
+        sb = cfma_r<C>(cscale<C>(sb, kin), vd, v.b);
+        inb.a = cmul<C>(c0a, sa);
+        inb.b = cmul<C>(c0b, sb);
+        s.a = cmul<C>(c0a, v.a);
+        s.b = cmul<C>(c0b, v.b);
         pdq[P] = v.b;
       }
     } else if (own) {
       const int iz = (m < 0) ? m + nz : m - nz;
       const int64_t n = base + tx + (int64_t)nx * y + plane * iz;
-      Pair<R> v = a.rin[n];
+      Pair<C> v = pcast<C, R>(a.rin[n]);
       if (BICG) {
-        const Pair<R> po = a.pold[n];
-        v.a = cfma<R>(v.a, ba, po.a);
-        v.b = cfma<R>(v.b, bb, po.b);
+        const Pair<C> po = pcast<C, R>(a.pold[n]);
+        v.a = cfma<C>(v.a, ba, po.a);
+        v.b = cfma<C>(v.b, bb, po.b);
+        v = pcast<C, R>(pcast<R, C>(v));   // as stored by the tile that owns the plane
       }
       if (m < 0) {
-        s.a = cmul<R>(cma, v.a);
-        s.b = cmul<R>(cmb, v.b);
+        s.a = cmul<C>(cma, v.a);
+        s.b = cmul<C>(cmb, v.b);
       } else {
-        s.a = cmul<R>(cpa, v.a);
-        s.b = cmul<R>(cpb, v.b);
+        s.a = cmul<C>(cpa, v.a);
+        s.b = cmul<C>(cpb, v.b);
       }
     }
     if (own) {
 #pragma unroll
       for (int d = 0; d <= 2 * P; ++d) {
-        acc[d].a = cfma_r<R>(acc[d].a, zc[d], s.a);
-        acc[d].b = cfma_r<R>(acc[d].b, zc[d], s.b);
+        acc[d].a = cfma_r<C>(acc[d].a, zc[d], s.a);
+        acc[d].b = cfma_r<C>(acc[d].b, zc[d], s.b);
       }
       if (real) {
-        acc[P].a = cadd<R>(acc[P].a, inb.a);
-        acc[P].b = cadd<R>(acc[P].b, inb.b);
+        acc[P].a = cadd<C>(acc[P].a, inb.a);
+        acc[P].b = cadd<C>(acc[P].b, inb.b);
       }
       const int o = m - P;
       if (o >= 0) {
-        a.q[base + tx + (int64_t)nx * y + plane * o] = acc[0];
+        a.q[base + tx + (int64_t)nx * y + plane * o] = pcast<R, C>(acc[0]);
         if (BICG) {
-          const cplx<R> t = cmulc<R>(pdq[0], acc[0].a);
+          const cplx<C> t = cmulc<C>(pdq[0], acc[0].a);
           sig.x += (double)t.x;
           sig.y += (double)t.y;
         }
       }
 #pragma unroll
       for (int d = 0; d < 2 * P; ++d) acc[d] = acc[d + 1];
-      acc[2 * P].a = mkc<R>(0, 0);
-      acc[2 * P].b = mkc<R>(0, 0);
+      acc[2 * P].a = mkc<C>(0, 0);
+      acc[2 * P].b = mkc<C>(0, 0);
 #pragma unroll
       for (int d = 0; d < P; ++d) pdq[d] = pdq[d + 1];
     }
@@ -260,8 +273,8 @@ int32_t default_tile_y(const cbs_system* s, int32_t bytes_per_pair) {
   return best;
 }
 
-template <typename R, int P, bool BICG>
-static int32_t launch_p(const cbs_system* s, const StArgs<R>& a, hipStream_t st) {
+template <typename R, typename C, int P, bool BICG>
+static int32_t launch_pc(const cbs_system* s, const StArgs<R>& a, hipStream_t st) {
   const int nthr = s->nx * a.ty;
   const size_t smem = (size_t)a.nbuf * (a.ty + 2 * P) * s->nx * sizeof(Pair<R>);
   if (smem > 64 * 1024) {
@@ -269,9 +282,15 @@ static int32_t launch_p(const cbs_system* s, const StArgs<R>& a, hipStream_t st)
     return CBS_EINVAL;
   }
   const int grid = (a.nlogical + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_stencil<R, P, BICG>), dim3(grid), dim3(nthr), smem, st, a);
+  hipLaunchKernelGGL((k_stencil<R, C, P, BICG>), dim3(grid), dim3(nthr), smem, st, a);
   CBS_HIP(hipGetLastError());
   return CBS_OK;
+}
+
+template <typename R, int P, bool BICG>
+static int32_t launch_p(const cbs_system* s, const StArgs<R>& a, hipStream_t st) {
+  if (std::is_same<R, float>::value && lo_arith_fp32()) return launch_pc<R, float, P, BICG>(s, a, st);
+  return launch_pc<R, double, P, BICG>(s, a, st);
 }
 
 template <typename R>
@@ -287,9 +306,10 @@ int32_t launch_stencil(const cbs_system* s, bool bicg, const StencilLaunch& l, i
   a.nbuf = ((size_t)2 * (tile_y + 2 * s->p) * s->nx * sizeof(Pair<R>) <= 64 * 1024) ? 2 : 1;
   a.nlogical = l.nruns * a.ntiles;
   a.N = s->N;
-  a.kin = (R)(-0.5 / (s->h * s->h));
-  for (int i = 0; i < 5; ++i) a.c[i] = (R)s->fd[i];
+  a.kin = -0.5 / (s->h * s->h);
+  for (int i = 0; i < 5; ++i) a.c[i] = s->fd[i];
   a.vloc = std::is_same<R, double>::value ? (const R*)s->vloc64 : (const R*)s->vloc32;
+  a.vloc64 = s->vloc64;
   a.rin = (const Pair<R>*)l.rin;
   a.pold = (const Pair<R>*)l.pold;
   a.pnew = (Pair<R>*)l.pnew;

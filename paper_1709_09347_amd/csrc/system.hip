@@ -157,6 +157,43 @@ static int32_t build_projectors(cbs_system* s, const cbs_proj* pr) {
       }
     }
   }
+  // grouped ket tables (groups of KG consecutive points, keys ascending per group)
+  const int64_t ngroups = (s->N + KG - 1) / KG;
+  std::vector<int32_t> grp_off(ngroups + 1, 0), grp_key;
+  std::vector<double> grp_u;
+  for (int64_t g = 0; g < ngroups; ++g) {
+    const int64_t n0 = g * KG, n1 = std::min<int64_t>(n0 + KG, s->N);
+    std::vector<int32_t> keys;
+    for (int64_t n = n0; n < n1; ++n)
+      for (int32_t e = cnt[n]; e < cnt[n + 1]; ++e) keys.push_back(pt_key[e]);
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    const size_t k0 = grp_key.size();
+    grp_key.insert(grp_key.end(), keys.begin(), keys.end());
+    grp_u.resize(grp_key.size() * KG * 4, 0.0);
+    for (int64_t n = n0; n < n1; ++n)
+      for (int32_t e = cnt[n]; e < cnt[n + 1]; ++e) {
+        const size_t k = k0 + (std::lower_bound(keys.begin(), keys.end(), pt_key[e]) - keys.begin());
+        // a ball wider than the transverse period reaches a point twice with the same
+        // key: the values add (both entries meet the same coefficient K)
+        for (int i = 0; i < 4; ++i) grp_u[(k * KG + (n - n0)) * 4 + i] += pt_u[4 * (size_t)e + i];
+      }
+    if (grp_key.size() >= ((size_t)1 << 31)) {
+      set_error("projectors: grouped ket table too large");
+      return CBS_EINVAL;
+    }
+    grp_off[g + 1] = (int32_t)grp_key.size();
+  }
+  if (grp_key.empty()) {   // keep the device pointers valid
+    grp_key.push_back(0);
+    grp_u.resize(KG * 4, 0.0);
+  }
+  std::vector<float> grp_u32(grp_u.begin(), grp_u.end());
+  P.grp_nkeys = (int64_t)grp_off[ngroups];
+  CBS_TRY(upload(grp_off, &P.grp_off));
+  CBS_TRY(upload(grp_key, &P.grp_key));
+  CBS_TRY(upload(grp_u, &P.grp_u64));
+  CBS_TRY(upload(grp_u32, &P.grp_u32));
   std::vector<float> u32(u64.begin(), u64.end()), ptu32(pt_u.begin(), pt_u.end()),
       cf32(cf.begin(), cf.end());
   P.n_atoms = A;
@@ -191,6 +228,10 @@ static void free_system(cbs_system* s) {
   f(P.pt_key);
   f(P.pt_u64);
   f(P.pt_u32);
+  f(P.grp_off);
+  f(P.grp_key);
+  f(P.grp_u64);
+  f(P.grp_u32);
   f(s->last.vecs);
   s->ws.release();
 }
