@@ -10,9 +10,9 @@ in device memory before the timed region.
 
 One step = one complete solve at one energy (BiCG with duals at all nodes, moments,
 Hankel SVD, Rayleigh-Ritz extraction, residuals).  The mixed-precision path (complex128
-BiCG until a run's residual is below 1e-3, complex64 vectors after that with
-complex128 residual replacement) is the reported value; the complex128 path is timed
-beside it on the same inputs.
+BiCG until a run's residual is below 1e-5, then complex64 vectors and FP32 operator
+applications with complex128 residual replacement) is the reported value; the
+complex128 path is timed beside it on the same inputs.
 
 The JSON line also carries the roofline of the dominant kernel (the BiCG stencil,
 timed per launch with HIP events on the stream it runs on in a diagnostic solve

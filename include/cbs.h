@@ -105,7 +105,7 @@ typedef struct {
                            with FP64 residual replacement (iterative refinement) to tol */
   int32_t extraction;   /* CBS_RR (default) or CBS_HANKEL */
   int32_t half_stop;    /* 1: stop all solves once more than half of the nodes converged (Sec. 3.3) */
-  double inner_tol;     /* CBS_MIXED: residual below which a run continues in complex64 (1e-3) */
+  double inner_tol;     /* CBS_MIXED: residual below which a run continues in complex64 (1e-5) */
   int32_t max_refine;   /* cap on FP64 residual replacements per run (60) */
   int32_t chunk;        /* iterations per captured graph between convergence polls (even) */
   int32_t profile;      /* 1: no graph; HIP events time every BiCG stencil launch (cbs_info.stencil_*) */

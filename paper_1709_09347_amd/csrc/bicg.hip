@@ -26,7 +26,7 @@
 // since the last one: the FP64 iterative refinement that keeps the gap between the
 // single-precision recursive residual and the true residual below the tolerance.  A run
 // whose true residual stops falling in complex64 restarts in complex128.  The complex64
-// phase stores complex64 but computes in FP64 (CBS_LO_ARITH=32: FP32).  FP64
+// phase computes in FP32 (CBS_LO_ARITH=64: FP64 arithmetic on complex64 data).  FP64
 // mode stays in the complex128 phase, where S2 only marks runs whose recursive residual
 // met tol.
 // The iteration is captured once into a HIP graph of `chunk` iterations and replayed

@@ -111,12 +111,12 @@ __device__ __forceinline__ int mfma16_row(int lane, int v) {
 #define CBS_CONST_AS
 #endif
 
-// Arithmetic precision of the complex64-storage kernels: FP64 by default (the HBM traffic
-// halves while the operator is applied as accurately as the rounding of its complex64
-// input and output allows); CBS_LO_ARITH=32 selects FP32 arithmetic.
+// Arithmetic precision of the complex64-storage kernels: FP32 by default (complex64
+// operator applications and updates; the phase starts once the residual is small enough
+// for them); CBS_LO_ARITH=64 computes in FP64 on the complex64 data.
 inline bool lo_arith_fp32() {
   const char* e = getenv("CBS_LO_ARITH");
-  return e && e[0] == '3' && e[1] == '2';
+  return !(e && e[0] == '6' && e[1] == '4');
 }
 
 __device__ __forceinline__ int xcd_remap(int bid, int nb) { return (bid & 7) * (nb >> 3) + (bid >> 3); }

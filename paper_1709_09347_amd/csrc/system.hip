@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "cbs_internal.hpp"
+#include "tables.hpp"
 
 namespace cbs {
 
@@ -157,39 +158,23 @@ static int32_t build_projectors(cbs_system* s, const cbs_proj* pr) {
       }
     }
   }
-  // grouped ket tables (groups of KG consecutive points, keys ascending per group)
-  const int64_t ngroups = (s->N + KG - 1) / KG;
-  std::vector<int32_t> grp_off(ngroups + 1, 0), grp_key;
-  std::vector<double> grp_u;
-  for (int64_t g = 0; g < ngroups; ++g) {
-    const int64_t n0 = g * KG, n1 = std::min<int64_t>(n0 + KG, s->N);
-    std::vector<int32_t> keys;
-    for (int64_t n = n0; n < n1; ++n)
-      for (int32_t e = cnt[n]; e < cnt[n + 1]; ++e) keys.push_back(pt_key[e]);
-    std::sort(keys.begin(), keys.end());
-    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-    const size_t k0 = grp_key.size();
-    grp_key.insert(grp_key.end(), keys.begin(), keys.end());
-    grp_u.resize(grp_key.size() * KG * 4, 0.0);
-    for (int64_t n = n0; n < n1; ++n)
-      for (int32_t e = cnt[n]; e < cnt[n + 1]; ++e) {
-        const size_t k = k0 + (std::lower_bound(keys.begin(), keys.end(), pt_key[e]) - keys.begin());
-        // a ball wider than the transverse period reaches a point twice with the same
-        // key: the values add (both entries meet the same coefficient K)
-        for (int i = 0; i < 4; ++i) grp_u[(k * KG + (n - n0)) * 4 + i] += pt_u[4 * (size_t)e + i];
-      }
-    if (grp_key.size() >= ((size_t)1 << 31)) {
-      set_error("projectors: grouped ket table too large");
-      return CBS_EINVAL;
-    }
-    grp_off[g + 1] = (int32_t)grp_key.size();
+  // grouped ket table (groups of KG consecutive points, keys ascending per group)
+  GroupTables gt;
+  const std::string why = build_group_tables(s->N, cnt, pt_key, pt_u, KG, gt);
+  if (!why.empty()) {
+    set_error("projectors: %s", why.c_str());
+    return CBS_EINVAL;
   }
+  std::vector<int32_t>& grp_off = gt.grp_off;
+  std::vector<int32_t>& grp_key = gt.grp_key;
+  std::vector<double>& grp_u = gt.grp_u;
+  const int64_t ngroups = (int64_t)grp_off.size() - 1;
+  P.grp_nkeys = (int64_t)grp_off[ngroups];
   if (grp_key.empty()) {   // keep the device pointers valid
     grp_key.push_back(0);
     grp_u.resize(KG * 4, 0.0);
   }
   std::vector<float> grp_u32(grp_u.begin(), grp_u.end());
-  P.grp_nkeys = (int64_t)grp_off[ngroups];
   CBS_TRY(upload(grp_off, &P.grp_off));
   CBS_TRY(upload(grp_key, &P.grp_key));
   CBS_TRY(upload(grp_u, &P.grp_u64));
@@ -363,7 +348,7 @@ void cbs_params_default(cbs_params* p) {
   p->precision = CBS_FP64;
   p->extraction = CBS_RR;
   p->half_stop = 0;
-  p->inner_tol = 1e-3;
+  p->inner_tol = 1e-5;
   p->max_refine = 60;
   p->chunk = 8;
 }
