@@ -32,9 +32,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "time per energy to 1e-10 residual (mixed vs FP64 GPU); stencil HBM GB/s"
-# HBM bytes per dispatch of the stencil from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB), scaled by
-# the copy-kernel calibration; None until the counters have been taken for the current kernel.
-STENCIL_TRAFFIC_BYTES = None
+# HBM traffic of the complex128 BiCG stencil relative to its algorithmic bytes, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE on full-batch dispatches of this workload, each scaled by what the
+# counter reads for a plain 1 GiB device copy (bench.py --copy-calibration); the commands and
+# raw figures are in profiles/stencil_fp64_48x48x32_counters.md.  None once the kernel changes.
+STENCIL_TRAFFIC_RATIO = 1.0556
 
 
 def cpu_baseline(sysw, E, V, iters_per_run, n_runs, budget_s=12.0):
@@ -137,21 +139,29 @@ def main():
 
     if args.legs != "both" or args.iters_cap > 0:
         return
-    # dominant kernel: the mixed path's BiCG stencil, timed per launch (diagnostic solve)
+    # dominant kernel of both paths: the complex128 BiCG stencil (timed per launch with HIP
+    # events in a diagnostic solve of the FP64 leg); the complex64 stencil of the mixed leg
+    # is reported beside it
     roof = {}
-    for name, prec in (("mixed", cbs.CBS_MIXED), ("fp64", cbs.CBS_FP64)):
+    for name, prec in (("fp64", cbs.CBS_FP64), ("mixed", cbs.CBS_MIXED)):
         prm = cbs.default_params(n_rhs=L, n_mom=M, precision=prec, profile=1)
         _, _, _, pinfo, _ = s.solve(E, V, prm, want_vectors=False)
-        avg_ms = pinfo.stencil_ms / max(pinfo.stencil_launches, 1)
-        avg_bytes = pinfo.stencil_bytes / max(pinfo.stencil_launches, 1)
+        if name == "fp64":
+            n_l, ms, by = pinfo.stencil_launches, pinfo.stencil_ms, pinfo.stencil_bytes
+            kern, ratio = "k_stencil<double,double,4,true>", STENCIL_TRAFFIC_RATIO
+        else:
+            n_l, ms, by = pinfo.stencil_lo_launches, pinfo.stencil_lo_ms, pinfo.stencil_lo_bytes
+            kern, ratio = "k_stencil<float,float,4,true>", None
+        avg_ms = ms / max(n_l, 1)
+        avg_bytes = by / max(n_l, 1)
         gbs = avg_bytes / (avg_ms * 1e-3) / 1e9
         roof[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": STENCIL_TRAFFIC_BYTES,
-                      "kernel": f"k_stencil<{'float' if prec else 'double'},4,true>",
-                      "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": avg_bytes,
-                      "launches": int(pinfo.stencil_launches)}
-        print(f"# stencil ({name}): {avg_ms:.3f} ms/launch, {gbs:.0f} GB/s over "
-              f"{pinfo.stencil_launches} launches", file=sys.stderr, flush=True)
+                      "frac": round(gbs / HBM_PEAK_GBS, 4),
+                      "traffic": (round(ratio * avg_bytes) if ratio is not None else None),
+                      "kernel": kern, "avg_launch_ms": round(avg_ms, 4),
+                      "algorithmic_bytes_per_launch": round(avg_bytes), "launches": int(n_l)}
+        print(f"# {kern} ({name} leg): {avg_ms:.3f} ms/launch, {gbs:.0f} GB/s over {n_l} launches",
+              file=sys.stderr, flush=True)
 
     mixed, fp64 = runs["mixed"], runs["fp64"]
     dl = qep.match_sets(mixed["lam"], fp64["lam"]) if len(mixed["lam"]) == len(fp64["lam"]) else None
@@ -177,8 +187,8 @@ def main():
         "lambda_rel_diff_mixed_vs_fp64": dl,
         "max_eig_resid": float(max(mixed["info"].max_eig_resid, fp64["info"].max_eig_resid)),
         "bicg_iters_mean": {"fp64": fp64["info"].iters_mean, "mixed": mixed["info"].iters_mean},
-        "roofline": roof["mixed"],
-        "roofline_fp64": roof["fp64"],
+        "roofline": roof["fp64"],
+        "roofline_complex64_stencil": roof["mixed"],
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sysw, E, Vh, fp64["info"].iters_mean, 32 * L)

@@ -126,10 +126,14 @@ typedef struct {
   int64_t matvecs;          /* operator applications (vectors) in the solves */
   /* params.profile = 1 only: the BiCG stencil kernel, timed per launch with HIP events on
    * the stream it runs on; bytes are its algorithmic traffic (per active run: read r,
-   * p_old, x and write p_new, q, x once, plus V_loc once per launch). */
+   * p_old, x and write p_new, q, x once, plus V_loc once per launch).  stencil_*: the
+   * complex128 kernel, stencil_lo_*: the complex64 kernel (CBS_MIXED). */
   int64_t stencil_launches;
   double stencil_ms;
   double stencil_bytes;
+  int64_t stencil_lo_launches;
+  double stencil_lo_ms;
+  double stencil_lo_bytes;
 } cbs_info;
 
 /* ---- errors ---------------------------------------------------------- */

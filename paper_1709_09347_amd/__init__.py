@@ -69,7 +69,8 @@ class Info(ctypes.Structure):
                 ("t_solve_ms", ctypes.c_double), ("t_moments_ms", ctypes.c_double),
                 ("t_extract_ms", ctypes.c_double), ("matvecs", ctypes.c_int64),
                 ("stencil_launches", ctypes.c_int64), ("stencil_ms", ctypes.c_double),
-                ("stencil_bytes", ctypes.c_double)]
+                ("stencil_bytes", ctypes.c_double), ("stencil_lo_launches", ctypes.c_int64),
+                ("stencil_lo_ms", ctypes.c_double), ("stencil_lo_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

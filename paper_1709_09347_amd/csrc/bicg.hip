@@ -807,16 +807,12 @@ int32_t bicg_collect(BicgSolve& b, NodeSolve& out, hipStream_t st) {
     }
   }
   out.Y = b.Y;
-  // the stencil of the phase that did most of the work
-  if (b.mixed) {
-    out.prof_launches = b.lo.prof_launches;
-    out.prof_ms = b.lo.prof_ms;
-    out.prof_bytes = b.lo.prof_bytes;
-  } else {
-    out.prof_launches = b.hi.prof_launches;
-    out.prof_ms = b.hi.prof_ms;
-    out.prof_bytes = b.hi.prof_bytes;
-  }
+  out.prof_launches = b.hi.prof_launches;
+  out.prof_ms = b.hi.prof_ms;
+  out.prof_bytes = b.hi.prof_bytes;
+  out.prof_lo_launches = b.lo.prof_launches;
+  out.prof_lo_ms = b.lo.prof_ms;
+  out.prof_lo_bytes = b.lo.prof_bytes;
   return CBS_OK;
 }
 
@@ -964,6 +960,9 @@ extern "C" int32_t cbs_bicg(cbs_system* s, double E, int32_t n_z, const double* 
     info->stencil_launches = ns.prof_launches;
     info->stencil_ms = ns.prof_ms;
     info->stencil_bytes = ns.prof_bytes;
+    info->stencil_lo_launches = ns.prof_lo_launches;
+    info->stencil_lo_ms = ns.prof_lo_ms;
+    info->stencil_lo_bytes = ns.prof_lo_bytes;
   }
   if (noconv) {
     set_error("cbs_bicg: some runs missed the tolerance");

@@ -84,8 +84,8 @@ struct NodeSolve {
   std::vector<int32_t> iters, status;
   std::vector<double> relres;
   double ms = 0;
-  int64_t prof_launches = 0;
-  double prof_ms = 0, prof_bytes = 0;
+  int64_t prof_launches = 0, prof_lo_launches = 0;   // complex128 / complex64 stencil
+  double prof_ms = 0, prof_bytes = 0, prof_lo_ms = 0, prof_lo_bytes = 0;
   int32_t n_ru = 0;
 };
 

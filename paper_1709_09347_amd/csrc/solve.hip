@@ -557,6 +557,9 @@ extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, con
     info->stencil_launches = ns.prof_launches;
     info->stencil_ms = ns.prof_ms;
     info->stencil_bytes = ns.prof_bytes;
+    info->stencil_lo_launches = ns.prof_lo_launches;
+    info->stencil_lo_ms = ns.prof_lo_ms;
+    info->stencil_lo_bytes = ns.prof_lo_bytes;
   }
   if (cnt > max_eigs) {
     set_error("cbs_solve: %d eigenvalues, output holds %d", cnt, max_eigs);
