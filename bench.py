@@ -137,6 +137,9 @@ def main():
               f"{info.max_solve_resid:.2e}, max eigen residual {info.max_eig_resid:.2e}, rc {rc}",
               file=sys.stderr, flush=True)
 
+    ty64, ty32, tune_log = s.tiling()
+    tiling = {"tile_y_c128": ty64, "tile_y_c64": ty32}
+    print(f"# stencil tiles: {tiling}; autotuner: {tune_log}", file=sys.stderr, flush=True)
     if args.legs != "both" or args.iters_cap > 0:
         return
     # dominant kernel of both paths: the complex128 BiCG stencil (timed per launch with HIP
@@ -187,6 +190,7 @@ def main():
         "lambda_rel_diff_mixed_vs_fp64": dl,
         "max_eig_resid": float(max(mixed["info"].max_eig_resid, fp64["info"].max_eig_resid)),
         "bicg_iters_mean": {"fp64": fp64["info"].iters_mean, "mixed": mixed["info"].iters_mean},
+        "stencil_tiles": tiling,
         "roofline": roof["fp64"],
         "roofline_complex64_stencil": roof["mixed"],
     }

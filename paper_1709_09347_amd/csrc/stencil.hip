@@ -118,6 +118,65 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
   for (int d = 0; d <= P; ++d) pdq[d] = mkc<C>(0, 0);
   double2 sig = make_double2(0.0, 0.0);
 
+  // Plane staging, software-pipelined: the loads of plane m+1 are issued into registers
+  // before plane m is computed and committed (direction update, stores, LDS) after it,
+  // when every thread holds at most PF elements of the region; otherwise load and commit
+  // happen together.
+  constexpr int PF = 2;
+  const bool pipe = region <= PF * nthr;
+  Pair<R> pr_r[PF], pr_p[PF], pr_x[PF];
+  auto issue = [&](int mm) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int e = tid + k * nthr;
+      if (e >= region) break;
+      const int r = e / nx;
+      const int xx = e - r * nx;
+      const int uy = y0 + r;
+      int gy = uy % ny;
+      if (gy < 0) gy += ny;
+      const int64_t n = base + xx + (int64_t)nx * gy + plane * mm;
+      pr_r[k] = a.rin[n];
+      if (BICG) {
+        pr_p[k] = a.pold[n];
+        if (do_x && r >= P && r < P + TY && uy < ny) pr_x[k] = a.x[n];
+      }
+    }
+  };
+  auto commit = [&](int mm, Pair<R>* buf) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int e = tid + k * nthr;
+      if (e >= region) break;
+      if (BICG) {
+        const int r = e / nx;
+        const int xx = e - r * nx;
+        const int uy = y0 + r;
+        int gy = uy % ny;
+        if (gy < 0) gy += ny;
+        const int64_t n = base + xx + (int64_t)nx * gy + plane * mm;
+        Pair<C> v = pcast<C, R>(pr_r[k]);
+        const Pair<C> po = pcast<C, R>(pr_p[k]);
+        v.a = cfma<C>(v.a, ba, po.a);
+        v.b = cfma<C>(v.b, bb, po.b);
+        const Pair<R> vs = pcast<R, C>(v);
+        if (r >= P && r < P + TY && uy < ny) {
+          a.pnew[n] = vs;
+          if (do_x) {
+            Pair<C> xv = pcast<C, R>(pr_x[k]);
+            xv.a = cfma<C>(xv.a, xa, po.a);
+            xv.b = cfma<C>(xv.b, xb, po.b);
+            a.x[n] = pcast<R, C>(xv);
+          }
+        }
+        buf[e] = vs;
+      } else {
+        buf[e] = pr_r[k];
+      }
+    }
+  };
+  if (pipe) issue(0);
+
   for (int m = -P; m < nz + P; ++m) {
     const bool real = (m >= 0) && (m < nz);
     Pair<C> s;
@@ -127,7 +186,11 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
     if (real) {
       Pair<R>* buf = lds + ((a.nbuf == 2) ? (m & 1) * region : 0);
       if (a.nbuf == 1 && m > 0) __syncthreads();   // single buffer: previous plane fully read
-      for (int e = tid; e < region; e += nthr) {
+      if (pipe) {
+        commit(m, buf);
+        if (m + 1 < nz) issue(m + 1);
+      }
+      for (int e = tid; e < region && !pipe; e += nthr) {
         const int r = e / nx;
         const int xx = e - r * nx;
         const int uy = y0 + r;
