@@ -721,6 +721,9 @@ int32_t bicg_run(std::vector<BicgSolve*>& solves, hipStream_t user, int32_t chun
   for (auto* b : solves) CBS_TRY(enqueue_init(*b, st));
   CBS_HIP(hipHostMalloc(&hact, sizeof(int32_t) * 2 * solves.size(), hipHostMallocDefault));
   const bool graphs = use_graphs() && !profile;
+  // CBS_VERBOSE=2: a progress line every 500 iterations (long solves)
+  const char* vb = getenv("CBS_VERBOSE");
+  const int progress = (vb && vb[0] == '2') ? 500 : 0;
   if (graphs) {
     CBS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
     int32_t rc = CBS_OK;
@@ -766,6 +769,10 @@ int32_t bicg_run(std::vector<BicgSolve*>& solves, hipStream_t user, int32_t chun
       int any = 0;
       for (size_t i = 0; i < 2 * solves.size(); ++i) any += hact[i];
       if (any == 0) break;
+      if (progress > 0 && (c + 1) * chunk % progress == 0) {
+        fprintf(stderr, "[cbs] BiCG iteration %d: %d runs active\n", (c + 1) * chunk, any);
+        fflush(stderr);
+      }
     }
   }
   CBS_HIP(hipStreamSynchronize(st));
@@ -790,7 +797,7 @@ int32_t bicg_collect(BicgSolve& b, NodeSolve& out, hipStream_t st) {
   out.n_ru = 0;
   for (int v : nru) out.n_ru = std::max(out.n_ru, v);
   const char* verbose = getenv("CBS_VERBOSE");
-  if (verbose && verbose[0] == '1') {
+  if (verbose && (verbose[0] == '1' || verbose[0] == '2')) {
     // diagnostics: final states, iteration spread, the slowest runs
     int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int v : out.status) cnt[(v >= 0 && v < 8) ? v : 0] += 1;
