@@ -104,13 +104,17 @@ __global__ void __launch_bounds__(256) k_partials(int64_t N, int32_t nchunks, in
 }
 
 // Residual replacement, first half: x += xcoef p (the pending update), y += x, x = 0.
+// Work items: (entry of the replacement list, chunk of points); runs of the other phase
+// are skipped.
 template <typename T>
-__global__ void __launch_bounds__(256) k_ru_pre(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* status,
-                                                int32_t need, const double2* xcoef, const Pair<T>* P, Pair<T>* X,
+__global__ void __launch_bounds__(256) k_ru_pre(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* list,
+                                                const int32_t* count, const int32_t* status, int32_t need,
+                                                const double2* xcoef, const Pair<T>* P, Pair<T>* X,
                                                 Pair<double>* Y) {
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  if (lb >= nlogical) return;
-  const int run = lb / nchunks, ch = lb - run * nchunks;
+  const int lb = remap_active(blockIdx.x, min(nlogical, *count * nchunks));
+  if (lb < 0) return;
+  const int slot = lb / nchunks, ch = lb - slot * nchunks;
+  const int run = list[slot];
   if (status[run] != need) return;
   const int64_t chunk = (N + nchunks - 1) / nchunks;
   const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
@@ -134,48 +138,75 @@ __global__ void __launch_bounds__(256) k_ru_pre(int64_t N, int32_t nchunks, int3
 }
 
 // Residual replacement, second half: r = v - P y in complex128 (Q64 holds the local
-// part, the ket adds the projectors); written as the working residual R (precision T)
-// and, when R64 is given, also in complex128 (needed when the run changes phase).
+// part; the ket of the projectors is added over the grouped table, 64-point groups with
+// lane = point and the coefficients of each key read uniformly); written as the working
+// residual R (precision T) and, when R64 is given, also in complex128 (needed when the
+// run changes phase).  Work items: (entry of the replacement list, chunk of groups).
 template <typename T>
-__global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int32_t nlogical, int32_t L,
-                                                 int32_t n_atoms, const int32_t* status, int32_t need,
-                                                 const double2* V, const double2* Vd, const Pair<double>* Q64,
-                                                 const Pair<double>* KT64, const int32_t* pt_off,
-                                                 const int32_t* pt_key, const double* pt_u, Pair<T>* R,
+__global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* list,
+                                                 const int32_t* count, int32_t L, int32_t n_atoms,
+                                                 const int32_t* status, int32_t need, const double2* V,
+                                                 const double2* Vd, const Pair<double>* Q64,
+                                                 const Pair<double>* KT64, const int32_t* grp_off,
+                                                 const int32_t* grp_key, const double* grp_u, Pair<T>* R,
                                                  Pair<double>* R64, double* part) {
   __shared__ double red[4][4];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  if (lb >= nlogical) return;
-  const int run = lb / nchunks, ch = lb - run * nchunks;
+  const int lb = remap_active(blockIdx.x, min(nlogical, *count * nchunks));
+  if (lb < 0) return;
+  const int slot = lb / nchunks, ch = lb - slot * nchunks;
+  const int run = __builtin_amdgcn_readfirstlane(list[slot]);
   if (status[run] != need) return;
-  const int64_t chunk = (N + nchunks - 1) / nchunks;
-  const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const double2* v = V + (int64_t)(run % L) * N;
   const double2* vdual = Vd + (int64_t)(run % L) * N;
+  typedef const CBS_CONST_AS int32_t* cint_p;
+  typedef const CBS_CONST_AS Pair<double>* ckt_p;
+  const cint_p goff = (cint_p)grp_off;
+  const cint_p gkey = (cint_p)grp_key;
+  const int64_t ngroups = (N + KG - 1) / KG;
+  const int64_t gpc = (ngroups + nchunks - 1) / nchunks;
+  const int64_t g0 = ch * gpc;
+  const int64_t g1 = (g0 + gpc < ngroups) ? g0 + gpc : ngroups;
   double s[4] = {0, 0, 0, 0};
-  for (int64_t n = lo + tid; n < hi; n += 256) {
-    const int64_t g = (int64_t)run * N + n;
-    Pair<double> q = Q64[g];
+  for (int64_t g = g0 + wv; g < g1; g += 4) {
+    const int64_t n = g * KG + lane;
+    Pair<double> k;
+    k.a = make_double2(0, 0);
+    k.b = k.a;
     if (n_atoms > 0) {
-      const Pair<double> k = ket_at<double>(n, (int64_t)run * n_atoms * 12, pt_off, pt_key, pt_u, KT64);
-      q.a = cadd<double>(q.a, k.a);
-      q.b = cadd<double>(q.b, k.b);
+      const ckt_p kt = (ckt_p)KT64 + (int64_t)run * n_atoms * 12;
+      const int e0 = goff[g], e1 = goff[g + 1];
+      for (int e = e0; e < e1; ++e) {
+        const int key = gkey[e];
+        const double4 uu = reinterpret_cast<const double4*>(grp_u)[(int64_t)e * KG + lane];
+        const double us[4] = {uu.x, uu.y, uu.z, uu.w};
+        const ckt_p kp = kt + (int64_t)(key >> 2) * 12 + (key & 3) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const Pair<double> kk = kp[i];
+          k.a = cfma_r<double>(k.a, us[i], kk.a);
+          k.b = cfma_r<double>(k.b, us[i], kk.b);
+        }
+      }
     }
-    const double2 vv = v[n];
-    Pair<double> r64;
-    r64.a = csub<double>(vv, q.a);
-    r64.b = csub<double>(vdual[n], q.b);
-    Pair<T> r;
-    r.a = ccast<T, double>(r64.a);
-    r.b = ccast<T, double>(r64.b);
-    R[g] = r;
-    if (R64 != nullptr) R64[g] = r64;
-    const cplx<T> rho = cmulc<T>(r.b, r.a);
-    s[0] += (double)rho.x;
-    s[1] += (double)rho.y;
-    s[2] += cabs2<double>(r64.a);
-    s[3] += cabs2<double>(r64.b);
+    if (n < N) {
+      const int64_t gi = (int64_t)run * N + n;
+      const Pair<double> q = Q64[gi];
+      Pair<double> r64;
+      r64.a = csub<double>(v[n], cadd<double>(q.a, k.a));
+      r64.b = csub<double>(vdual[n], cadd<double>(q.b, k.b));
+      Pair<T> r;
+      r.a = ccast<T, double>(r64.a);
+      r.b = ccast<T, double>(r64.b);
+      R[gi] = r;
+      if (R64 != nullptr) R64[gi] = r64;
+      const cplx<T> rho = cmulc<T>(r.b, r.a);
+      s[0] += (double)rho.x;
+      s[1] += (double)rho.y;
+      s[2] += cabs2<double>(r64.a);
+      s[3] += cabs2<double>(r64.b);
+    }
   }
   for (int k = 0; k < 4; ++k) s[k] = wsum<double>(s[k]);
   if (lane == 0)
@@ -289,6 +320,31 @@ __device__ void build_lists(BicgScal& sc, int32_t nruns) {
 }
 __device__ __forceinline__ bool is_ru(int st) { return st == ST_RU_LO || st == ST_RU_HI; }
 
+// Compact list of the runs marked for residual replacement (either phase, ascending) in
+// list[2][.], count n_active[2].  One block of 256 threads.
+__device__ void build_ru_list(BicgScal& sc, int32_t nruns) {
+  __shared__ int wcnt[4];
+  __shared__ int base;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) base = 0;
+  __syncthreads();
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r0 = 0; r0 < nruns; r0 += 256) {
+    const int run = r0 + tid;
+    const bool ru = (run < nruns) && is_ru(sc.status[run]);
+    const unsigned long long m = __ballot(ru);
+    if (lane == 0) wcnt[wv] = __popcll(m);
+    __syncthreads();
+    int o = base;
+    for (int w = 0; w < wv; ++w) o += wcnt[w];
+    if (ru) sc.list[2 * (int64_t)nruns + o + __popcll(m & below)] = run;
+    __syncthreads();
+    if (tid == 0) base += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  if (tid == 0) sc.n_active[2] = base;
+}
+
 __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
                                             int32_t start) {
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
@@ -381,6 +437,8 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
       sc.ru_thr[run] = fmax(rr, rrt) * ru_factor;
     }
   }
+  __syncthreads();
+  build_ru_list(sc, nruns);
 }
 
 __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
@@ -459,6 +517,8 @@ __global__ void __launch_bounds__(256) k_half_stop(BicgScal sc, int32_t ngroups,
       }
     }
   }
+  __syncthreads();
+  build_ru_list(sc, ngroups * n_q * L);
 }
 
 // ------------------------------------------------------------------ host driver
@@ -506,9 +566,9 @@ int32_t bicg_alloc(BicgSolve& b, const char* tag) {
   CBS_TRY(ws_get(ws, (t + ".halt").c_str(), R, &b.sc.halt));
   CBS_TRY(ws_get(ws, (t + ".nru").c_str(), R, &b.sc.nru));
   CBS_TRY(ws_get(ws, (t + ".conv").c_str(), R, &b.sc.conv));
-  CBS_TRY(ws_get(ws, (t + ".nact").c_str(), 2, &b.sc.n_active));
+  CBS_TRY(ws_get(ws, (t + ".nact").c_str(), 3, &b.sc.n_active));
   CBS_TRY(ws_get(ws, (t + ".ruit").c_str(), R, &b.sc.ru_it));
-  CBS_TRY(ws_get(ws, (t + ".list").c_str(), 2 * R, &b.sc.list));
+  CBS_TRY(ws_get(ws, (t + ".list").c_str(), 3 * R, &b.sc.list));
   return CBS_OK;
 }
 
@@ -578,36 +638,38 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
     hipLaunchKernelGGL(k_half_stop, dim3(1), dim3(256), 0, st, b.sc, b.nruns / (b.n_q * b.L), b.n_q, b.L);
     CBS_HIP(hipGetLastError());
   }
-  // residual replacement of the marked runs
+  // residual replacement of the runs on the list built by k_s2 (and k_half_stop)
+  const int32_t* rul = b.sc.list + 2 * (size_t)b.nruns;
+  const int32_t* ruc = b.sc.n_active + 2;
   if (b.mixed)
-    hipLaunchKernelGGL(k_ru_pre<float>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl,
+    hipLaunchKernelGGL(k_ru_pre<float>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, rul, ruc,
                        (const int32_t*)b.sc.status, (int32_t)ST_RU_LO, (const double2*)b.sc.xcoef,
                        (const Pair<float>*)b.lo.Pb[parity & 1], b.lo.X, b.Y);
-  hipLaunchKernelGGL(k_ru_pre<double>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl,
+  hipLaunchKernelGGL(k_ru_pre<double>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, rul, ruc,
                      (const int32_t*)b.sc.status, (int32_t)ST_RU_HI, (const double2*)b.sc.xcoef,
                      (const Pair<double>*)b.hi.Pb[parity & 1], b.hi.X, b.Y);
   CBS_HIP(hipGetLastError());
-  for (int ph = b.mixed ? 0 : 1; ph < 2; ++ph) {
-    const int32_t need = ph ? ST_RU_HI : ST_RU_LO;
+  {
     StencilLaunch r{};
     r.nruns = b.nruns;
     r.rin = b.Y;
     r.q = b.hi.Q;
     r.coef = b.coef;
-    r.status = b.sc.status;
-    r.need_status = need;
+    r.list = rul;
+    r.count = ruc;
     CBS_TRY(launch_stencil<double>(s, false, r, b.hi.tile_y, st));
-    if (na > 0) CBS_TRY(launch_bra<double>(s, b.nruns, b.Y, b.coef, b.sc.status, need, b.hi.KT, nullptr, st, true));
+    if (na > 0)
+      CBS_TRY(launch_bra<double>(s, b.nruns, b.Y, b.coef, nullptr, 0, b.hi.KT, nullptr, st, true, rul, ruc));
   }
   if (b.mixed)
-    hipLaunchKernelGGL(k_ru_post<float>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, b.L, na,
-                       (const int32_t*)b.sc.status, (int32_t)ST_RU_LO, b.V, b.Vd ? b.Vd : b.V, (const Pair<double>*)b.hi.Q,
-                       (const Pair<double>*)b.hi.KT, s->proj.pt_off, s->proj.pt_key, (const double*)s->proj.pt_u64,
-                       b.lo.R, b.hi.R, b.ru_part);
-  hipLaunchKernelGGL(k_ru_post<double>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, b.L, na,
-                     (const int32_t*)b.sc.status, (int32_t)ST_RU_HI, b.V, b.Vd ? b.Vd : b.V, (const Pair<double>*)b.hi.Q,
-                     (const Pair<double>*)b.hi.KT, s->proj.pt_off, s->proj.pt_key, (const double*)s->proj.pt_u64,
-                     b.hi.R, (Pair<double>*)nullptr, b.ru_part);
+    hipLaunchKernelGGL(k_ru_post<float>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, rul, ruc, b.L, na,
+                       (const int32_t*)b.sc.status, (int32_t)ST_RU_LO, b.V, b.Vd ? b.Vd : b.V,
+                       (const Pair<double>*)b.hi.Q, (const Pair<double>*)b.hi.KT, s->proj.grp_off, s->proj.grp_key,
+                       (const double*)s->proj.grp_u64, b.lo.R, b.hi.R, b.ru_part);
+  hipLaunchKernelGGL(k_ru_post<double>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, rul, ruc, b.L, na,
+                     (const int32_t*)b.sc.status, (int32_t)ST_RU_HI, b.V, b.Vd ? b.Vd : b.V,
+                     (const Pair<double>*)b.hi.Q, (const Pair<double>*)b.hi.KT, s->proj.grp_off, s->proj.grp_key,
+                     (const double*)s->proj.grp_u64, b.hi.R, (Pair<double>*)nullptr, b.ru_part);
   CBS_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_s3, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.ru_part, b.tol,
                      b.max_iter, b.max_ru, b.ru_factor);
@@ -721,9 +783,12 @@ int32_t bicg_run(std::vector<BicgSolve*>& solves, hipStream_t user, int32_t chun
   for (auto* b : solves) CBS_TRY(enqueue_init(*b, st));
   CBS_HIP(hipHostMalloc(&hact, sizeof(int32_t) * 2 * solves.size(), hipHostMallocDefault));
   const bool graphs = use_graphs() && !profile;
-  // CBS_VERBOSE=2: a progress line every 500 iterations (long solves)
+  // CBS_VERBOSE=2: a progress line every 500 iterations (long solves); 3: one line per chunk
+  // with the complex128 / complex64 active-run counts and the chunk's wall time
   const char* vb = getenv("CBS_VERBOSE");
   const int progress = (vb && vb[0] == '2') ? 500 : 0;
+  const bool trace = vb && vb[0] == '3';
+  auto tc = std::chrono::steady_clock::now();
   if (graphs) {
     CBS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
     int32_t rc = CBS_OK;
@@ -768,6 +833,14 @@ int32_t bicg_run(std::vector<BicgSolve*>& solves, hipStream_t user, int32_t chun
       }
       int any = 0;
       for (size_t i = 0; i < 2 * solves.size(); ++i) any += hact[i];
+      if (trace) {
+        int hi = 0, lo = 0;
+        for (size_t i = 0; i < solves.size(); ++i) lo += hact[2 * i], hi += hact[2 * i + 1];
+        const auto now = std::chrono::steady_clock::now();
+        fprintf(stderr, "[cbs] chunk end %d: active complex128 %d complex64 %d, %.3f ms\n", (c + 1) * chunk, hi,
+                lo, std::chrono::duration<double, std::milli>(now - tc).count());
+        tc = now;
+      }
       if (any == 0) break;
       if (progress > 0 && (c + 1) * chunk % progress == 0) {
         fprintf(stderr, "[cbs] BiCG iteration %d: %d runs active\n", (c + 1) * chunk, any);

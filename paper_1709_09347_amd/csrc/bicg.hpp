@@ -38,8 +38,9 @@ struct BicgScal {
   int32_t* nru;
   int32_t* conv;      // phase change this iteration: 1 widen to complex128, 2 narrow to complex64
   int32_t* ru_it;     // iteration of the last replacement (complex64 stagnation guard)
-  int32_t* n_active;  // [2]: active runs in the complex64 / complex128 phase
-  int32_t* list;      // [2][nruns]: the active runs of each phase, ascending (n_active entries)
+  int32_t* n_active;  // [3]: active runs in the complex64 / complex128 phase; runs marked
+                      // for residual replacement
+  int32_t* list;      // [3][nruns]: the runs of each of those sets, ascending (n_active entries)
 };
 
 // Vectors of one precision (pairs: primal, dual per point, run-major).

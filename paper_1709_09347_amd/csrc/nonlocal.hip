@@ -44,9 +44,11 @@ __global__ void __launch_bounds__(256) k_bra(BraArgs<R> a) {
   __shared__ R red[4][16];
   __shared__ cplx<R> G[3][4][2];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  if (lb >= a.nlogical) return;
-  const int run = lb / a.n_atoms;
-  const int atom = lb - run * a.n_atoms;
+  const int nl = (a.list != nullptr) ? min(a.nlogical, *a.count * a.n_atoms) : a.nlogical;
+  if (lb >= nl) return;
+  const int slot = lb / a.n_atoms;
+  const int atom = lb - slot * a.n_atoms;
+  const int run = (a.list != nullptr) ? a.list[slot] : slot;
   if (a.status != nullptr && a.status[run] != a.need_status) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t base = (int64_t)run * a.N;
@@ -164,7 +166,7 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
   // Every wave covers all 16 runs (four groups g of 4 runs: four independent MFMA chains
   // that share each table load) over every 4th step of 4 ball entries; the four waves'
   // partial products are summed through LDS.
-  __shared__ C red[4][4][64][4];
+  __shared__ C red[4][4][16][4];
   const int row = lane & 15, kslot = lane >> 4, col = lane & 15;
   const int half = (row >> 1) & 1, reim = row & 1;
   const cplx<R>* vrow[4];
@@ -182,37 +184,76 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
   typename mf4<C>::T acc[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) acc[g] = {0, 0, 0, 0};
-  for (int e0 = s0 + 4 * wv; e0 < s3; e0 += 16) {
-    const int e = e0 + kslot;
-    const bool ok = e < s3;
-    int idx = 0;
-    C bv = 0;
-    if (ok) {
-      idx = a.idx[e];
-      if (col < 4) bv = (C)a.u[4 * (int64_t)e + col];
+  // FP64 arithmetic: the table entries (point index, projector value) of the next step
+  // of 4 ball entries are loaded while the gathers of this step are in flight, so each
+  // step waits for one memory latency rather than for the table load and then the gather
+  // that depends on it.  (With FP32 arithmetic the plain loop is faster: more waves fit.)
+  if constexpr (sizeof(C) == 8) {
+    const int e_first = s0 + 4 * wv + kslot;
+    int idx0 = 0;
+    C bv0 = 0;
+    if (e_first < s3) {
+      idx0 = a.idx[e_first];
+      if (col < 4) bv0 = (C)a.u[4 * (int64_t)e_first + col];
     }
-    cplx<C> vv[4];
+    for (int e = e_first; e - kslot < s3; e += 16) {
+      cplx<C> vv[4];
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
-      vv[g] = (ok && rvalid[g]) ? ccast<C, R>(vrow[g][2 * (int64_t)idx]) : mkc<C>(0, 0);
+      for (int g = 0; g < 4; ++g)
+        vv[g] = (e < s3 && rvalid[g]) ? ccast<C, R>(vrow[g][2 * (int64_t)idx0]) : mkc<C>(0, 0);
+      const int e1 = e + 16;
+      int idx1 = 0;
+      C bv1 = 0;
+      if (e1 < s3) {
+        idx1 = a.idx[e1];
+        if (col < 4) bv1 = (C)a.u[4 * (int64_t)e1 + col];
+      }
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const cplx<C> p = (e < s1) ? cmul<C>(zm[g], vv[g]) : (e < s2) ? vv[g] : cmul<C>(zp[g], vv[g]);
-      acc[g] = mfma16x16x4(reim ? p.y : p.x, bv, acc[g]);
+      for (int g = 0; g < 4; ++g) {
+        const cplx<C> p = (e < s1) ? cmul<C>(zm[g], vv[g]) : (e < s2) ? vv[g] : cmul<C>(zp[g], vv[g]);
+        acc[g] = mfma16x16x4(reim ? p.y : p.x, bv0, acc[g]);
+      }
+      idx0 = idx1;
+      bv0 = bv1;
+    }
+  } else {
+    for (int e0 = s0 + 4 * wv; e0 < s3; e0 += 16) {
+      const int e = e0 + kslot;
+      const bool ok = e < s3;
+      int idx = 0;
+      C bv = 0;
+      if (ok) {
+        idx = a.idx[e];
+        if (col < 4) bv = (C)a.u[4 * (int64_t)e + col];
+      }
+      cplx<C> vv[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        vv[g] = (ok && rvalid[g]) ? ccast<C, R>(vrow[g][2 * (int64_t)idx]) : mkc<C>(0, 0);
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const cplx<C> p = (e < s1) ? cmul<C>(zm[g], vv[g]) : (e < s2) ? vv[g] : cmul<C>(zp[g], vv[g]);
+        acc[g] = mfma16x16x4(reim ? p.y : p.x, bv, acc[g]);
+      }
     }
   }
+  // only the lanes of output columns 0..3 (the four projectors) carry results
+  if ((lane & 15) < 4) {
+    const int q = (lane >> 4) * 4 + (lane & 15);
 #pragma unroll
-  for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < 4; ++g)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[wv][g][lane][v] = acc[g][v];
+      for (int v = 0; v < 4; ++v) red[wv][g][q][v] = acc[g][v];
+  }
   __syncthreads();
   {
     // thread t < 256: group g = t/64 reduces lane t%64 over the four waves
     const int g = tid >> 6, l2 = tid & 63;
     if ((l2 & 15) < 4) {
+      const int q = (l2 >> 4) * 4 + (l2 & 15);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const C sum = red[0][g][l2][v] + red[1][g][l2][v] + red[2][g][l2][v] + red[3][g][l2][v];
+        const C sum = red[0][g][q][v] + red[1][g][q][v] + red[2][g][q][v] + red[3][g][q][v];
         const int r = mfma16_row<C>(l2, v);   // output row held by lane l2
         C* dst = reinterpret_cast<C*>(&cs[4 * g + (r >> 2)][(r >> 1) & 1][l2 & 15]);
         dst[r & 1] = sum;
@@ -273,8 +314,8 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
   a.status = status;
   a.kt = (Pair<R>*)kt;
   a.signl = signl;
-  a.list = nullptr;   // the plain bra filters by status
-  a.count = nullptr;
+  a.list = list;   // runs: the list entries, or all runs (both filtered by status if given)
+  a.count = count;
   const char* bm = getenv("CBS_BRA_MAP");
   a.spread = !(bm && bm[0] == 'x');
   if ((list == nullptr) != (count == nullptr)) {
@@ -282,8 +323,6 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
     return CBS_EINVAL;
   }
   if (phased && !bra_plain()) {
-    a.list = list;
-    a.count = count;
     a.nlogical = ((nruns + 15) / 16) * pr.n_atoms;
     const int grid = (a.nlogical + 7) / 8 * 8;
     if (std::is_same<R, float>::value && lo_arith_fp32())
@@ -321,22 +360,32 @@ struct UpdArgs {
   const R* grp_u;
 };
 
-// One workgroup updates UR runs (consecutive active-list slots) over a chunk of point
-// groups; a wave takes one group of KG = 64 points at a time (lane = point).  The ket
-// walks the group's keys (atom, shift): every lane reads its four projector values for
-// the key (zero outside that ball) and the coefficients K of the key are the same for
-// all lanes (uniform loads), so no lane gathers per entry.
+// One workgroup updates UR = 4 runs (consecutive active-list slots) over a chunk of point
+// groups; a wave takes one group of KG = 64 points at a time.  The ket of a group is a
+// small product on the matrix cores: for each of the group's keys (atom, shift), U [64
+// points x 4 projectors] (the grouped table) times K [4 projectors x 16 columns] (4 runs x
+// primal/dual x re/im), accumulated over the keys with MFMA 16x16x4 in four 16-point row
+// blocks.  One vector load brings a key's K operand for all four runs; keys go in
+// batches (two in FP64, four in FP32 arithmetic) whose loads are issued while the
+// previous batch is on the matrix cores.  The 64 x 16 result goes through LDS to lane =
+// point for the update of r.
 constexpr int UR = 4;
 
 template <typename R, typename C>
 __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
+  constexpr int KB = sizeof(C) == 8 ? 2 : 4;   // keys per batch
   __shared__ double red[4][UR][4];
+  __shared__ C tile[4][KG][17];
   const int nslots = (a.list != nullptr) ? *a.count : a.nruns;
-  const int nl = min(a.nlogical, ((nslots + UR - 1) / UR) * a.nchunks);
+  const int nrc = (nslots + UR - 1) / UR;
+  const int nl = min(a.nlogical, nrc * a.nchunks);
   const int lb = remap_active(blockIdx.x, nl);
   if (lb < 0) return;
-  const int rc = lb / a.nchunks;
-  const int ch = lb - rc * a.nchunks;
+  // run groups vary fastest: the workgroups that one XCD has in flight share a chunk of
+  // point groups, so its slice of the grouped table is fetched into that XCD's L2 once
+  // rather than once per run group
+  const int ch = lb / nrc;
+  const int rc = lb - ch * nrc;
   int run[UR];
   bool act[UR];
   bool any = false;
@@ -361,9 +410,7 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
     const double2 al = act[k] ? a.alpha[run[k]] : make_double2(0, 0);
     aa[k] = mkc<C>((C)al.x, (C)al.y);
   }
-  // the tables indexed by wave-uniform values are read through the scalar unit
   typedef const CBS_CONST_AS int32_t* cint_p;
-  typedef const CBS_CONST_AS Pair<R>* ckt_p;
   const cint_p goff = (cint_p)a.grp_off;
   const cint_p gkey = (cint_p)a.grp_key;
   const int64_t ngroups = (a.N + KG - 1) / KG;
@@ -371,60 +418,103 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
   const int64_t g0 = ch * gpc;
   const int64_t g1 = (g0 + gpc < ngroups) ? g0 + gpc : ngroups;
   const int64_t kstride = (int64_t)a.n_atoms * 12;
+  // MFMA operand roles: lane l feeds U[point l%16 of a row block][projector l/16] and
+  // K[projector l/16][column l%16], column c = 4 * run slot + 2 * (dual) + (imaginary)
+  const int orow = lane & 15, ok4 = lane >> 4;
+  const int bslot = orow >> 2;
+  const int krun = bslot == 0 ? run[0] : bslot == 1 ? run[1] : bslot == 2 ? run[2] : run[3];
+  const R* kcol = (a.kt != nullptr)
+                      ? reinterpret_cast<const R*>(a.kt + (int64_t)krun * kstride) + (orow & 3) + 4 * ok4
+                      : nullptr;
   double s[UR][4];
 #pragma unroll
   for (int k = 0; k < UR; ++k) s[k][0] = s[k][1] = s[k][2] = s[k][3] = 0;
   for (int64_t g = g0 + wv; g < g1; g += 4) {
-    const int64_t n = g * KG + lane;
-    const bool ok = n < a.N;
-    Pair<C> kq[UR];
+    typename mf4<C>::T acc[4];
 #pragma unroll
-    for (int k = 0; k < UR; ++k) {
-      kq[k].a = mkc<C>(0, 0);
-      kq[k].b = kq[k].a;
-    }
-    if (a.kt != nullptr) {
+    for (int rb = 0; rb < 4; ++rb) acc[rb] = {0, 0, 0, 0};
+    if (kcol != nullptr) {
       const int e0 = goff[g], e1 = goff[g + 1];
-      for (int e = e0; e < e1; ++e) {
-        const int key = gkey[e];
-        const typename vec4<R>::T uu = reinterpret_cast<const typename vec4<R>::T*>(a.grp_u)[(int64_t)e * KG + lane];
-        const C us[4] = {(C)uu.x, (C)uu.y, (C)uu.z, (C)uu.w};
-        const int64_t koff = (int64_t)(key >> 2) * 12 + (key & 3) * 4;
+      for (int eb = e0; eb < e1; eb += 64) {
+        // up to 64 keys of the group in one vector load (lane j holds key eb + j); the
+        // batches read them with readlane, so no scalar load waits inside the loop
+        const int nk = min(64, e1 - eb);
+        const int keyv = (lane < nk) ? a.grp_key[eb + lane] : 0;
+        C kbA[KB], ubA[KB][4], kbB[KB], ubB[KB][4];
+        // operands of keys j0 .. j0+KB-1 of this chunk (zero K past the last key)
+        auto load = [&](int j0, C (&kb)[KB], C (&ub)[KB][4]) {
 #pragma unroll
-        for (int k = 0; k < UR; ++k) {
-          if (!act[k]) continue;
-          const ckt_p kp = (ckt_p)a.kt + (int64_t)run[k] * kstride + koff;
+          for (int j = 0; j < KB; ++j) {
+            const bool valid = j0 + j < nk;   // wave-uniform
+            const int jj = valid ? j0 + j : 0;
+            const int key = __builtin_amdgcn_readlane(keyv, jj);
+            const int koff = (key >> 2) * 12 + (key & 3) * 4;
+            const C kv = (C)kcol[4 * koff];
+            kb[j] = valid ? kv : (C)0;
+            const R* up = a.grp_u + ((int64_t)(eb + jj) * KG + orow) * 4 + ok4;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const Pair<R> kr = kp[i];
-            const Pair<C> kk = pcast<C, R>(kr);
-            kq[k].a = cfma_r<C>(kq[k].a, us[i], kk.a);
-            kq[k].b = cfma_r<C>(kq[k].b, us[i], kk.b);
+            for (int rb = 0; rb < 4; ++rb) ub[j][rb] = (C)up[64 * rb];
           }
+        };
+        auto mma = [&](const C (&kb)[KB], const C (&ub)[KB][4]) {
+#pragma unroll
+          for (int j = 0; j < KB; ++j)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) acc[rb] = mfma16x16x4(ub[j][rb], kb[j], acc[rb]);
+        };
+        // two register buffers: the loads of the next batch are in flight while the
+        // MFMAs of the current one run
+        load(0, kbA, ubA);
+        for (int j0 = 0; j0 < nk; j0 += 2 * KB) {
+          load(j0 + KB, kbB, ubB);
+          mma(kbA, ubA);
+          if (j0 + KB >= nk) break;
+          load(j0 + 2 * KB, kbA, ubA);
+          mma(kbB, ubB);
         }
       }
     }
-    if (ok) {
+    // the 64 x 16 ket tile to lane = point (wave-private LDS rows)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tile[wv][16 * rb + mfma16_row<C>(lane, v)][orow] = acc[rb][v];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const C* kt = tile[wv][lane];
+    const int64_t n = g * KG + lane;
+    if (n < a.N) {
+      Pair<C> q[UR], r[UR];
+#pragma unroll
+      for (int k = 0; k < UR; ++k) {
+        const int64_t gi = (int64_t)run[k] * a.N + n;
+        q[k] = pcast<C, R>(a.q[gi]);
+        r[k] = pcast<C, R>(a.r[gi]);
+      }
 #pragma unroll
       for (int k = 0; k < UR; ++k) {
         if (!act[k]) continue;
-        const int64_t gi = (int64_t)run[k] * a.N + n;
-        Pair<C> q = pcast<C, R>(a.q[gi]);
-        q.a = cadd<C>(q.a, kq[k].a);
-        q.b = cadd<C>(q.b, kq[k].b);
-        Pair<C> r = pcast<C, R>(a.r[gi]);
-        r.a = csub<C>(r.a, cmul<C>(aa[k], q.a));
-        r.b = csub<C>(r.b, cmul<C>(cconj<C>(aa[k]), q.b));
-        const Pair<R> rs = pcast<R, C>(r);
-        a.r[gi] = rs;
-        r = pcast<C, R>(rs);   // the dots of the stored residual
-        const cplx<C> rho = cmulc<C>(r.b, r.a);
+        Pair<C> qk = q[k];
+        qk.a = cadd<C>(qk.a, mkc<C>(kt[4 * k], kt[4 * k + 1]));
+        qk.b = cadd<C>(qk.b, mkc<C>(kt[4 * k + 2], kt[4 * k + 3]));
+        Pair<C> rk = r[k];
+        rk.a = csub<C>(rk.a, cmul<C>(aa[k], qk.a));
+        rk.b = csub<C>(rk.b, cmul<C>(cconj<C>(aa[k]), qk.b));
+        const Pair<R> rs = pcast<R, C>(rk);
+        a.r[(int64_t)run[k] * a.N + n] = rs;
+        rk = pcast<C, R>(rs);   // the dots of the stored residual
+        const cplx<C> rho = cmulc<C>(rk.b, rk.a);
         s[k][0] += (double)rho.x;
         s[k][1] += (double)rho.y;
-        s[k][2] += (double)cabs2<C>(r.a);
-        s[k][3] += (double)cabs2<C>(r.b);
+        s[k][2] += (double)cabs2<C>(rk.a);
+        s[k][3] += (double)cabs2<C>(rk.b);
       }
     }
+    // the tile rows are rewritten by the next group
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 #pragma unroll
   for (int k = 0; k < UR; ++k)
