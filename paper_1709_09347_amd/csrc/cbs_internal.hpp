@@ -223,9 +223,11 @@ struct Projector {
   int32_t max_atom_entries = 0;
   // grouped ket tables: points in groups of KG consecutive indices; group g uses the
   // keys [grp_off[g], grp_off[g+1]) (atom*4 + (w+1), ascending) and for each key the
-  // values of its KG points (zero where the point is outside that ball)
+  // values of its KG points (zero where the point is outside that ball); grp_mask: per key
+  // one bit per 16-point block of the group with a nonzero value
   int32_t* grp_off = nullptr;    // [ngroups+1]
   int32_t* grp_key = nullptr;    // [nkeys]
+  int32_t* grp_mask = nullptr;   // [nkeys]
   double* grp_u64 = nullptr;     // [nkeys][KG][4]
   float* grp_u32 = nullptr;
   int64_t grp_nkeys = 0;

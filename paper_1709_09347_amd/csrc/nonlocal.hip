@@ -357,6 +357,7 @@ struct UpdArgs {
   const int32_t* count;   // device count of list entries
   const int32_t* grp_off;   // grouped ket tables (see Projector)
   const int32_t* grp_key;
+  const int32_t* grp_mask;
   const R* grp_u;
 };
 
@@ -440,37 +441,41 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
         // batches read them with readlane, so no scalar load waits inside the loop
         const int nk = min(64, e1 - eb);
         const int keyv = (lane < nk) ? a.grp_key[eb + lane] : 0;
+        const int maskv = (lane < nk) ? a.grp_mask[eb + lane] : 0;
         C kbA[KB], ubA[KB][4], kbB[KB], ubB[KB][4];
-        // operands of keys j0 .. j0+KB-1 of this chunk (zero K past the last key)
-        auto load = [&](int j0, C (&kb)[KB], C (&ub)[KB][4]) {
+        int mA[KB], mB[KB];
+        // operands of keys j0 .. j0+KB-1 of this chunk (no blocks past the last key; the
+        // 16-point blocks where the key's table is zero are neither loaded nor multiplied)
+        auto load = [&](int j0, C (&kb)[KB], C (&ub)[KB][4], int (&m)[KB]) {
 #pragma unroll
           for (int j = 0; j < KB; ++j) {
             const bool valid = j0 + j < nk;   // wave-uniform
             const int jj = valid ? j0 + j : 0;
             const int key = __builtin_amdgcn_readlane(keyv, jj);
+            m[j] = valid ? __builtin_amdgcn_readlane(maskv, jj) : 0;
             const int koff = (key >> 2) * 12 + (key & 3) * 4;
-            const C kv = (C)kcol[4 * koff];
-            kb[j] = valid ? kv : (C)0;
+            kb[j] = (C)kcol[4 * koff];
             const R* up = a.grp_u + ((int64_t)(eb + jj) * KG + orow) * 4 + ok4;
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) ub[j][rb] = (C)up[64 * rb];
+            for (int rb = 0; rb < 4; ++rb) ub[j][rb] = ((m[j] >> rb) & 1) ? (C)up[64 * rb] : (C)0;
           }
         };
-        auto mma = [&](const C (&kb)[KB], const C (&ub)[KB][4]) {
+        auto mma = [&](const C (&kb)[KB], const C (&ub)[KB][4], const int (&m)[KB]) {
 #pragma unroll
           for (int j = 0; j < KB; ++j)
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) acc[rb] = mfma16x16x4(ub[j][rb], kb[j], acc[rb]);
+            for (int rb = 0; rb < 4; ++rb)
+              if ((m[j] >> rb) & 1) acc[rb] = mfma16x16x4(ub[j][rb], kb[j], acc[rb]);
         };
         // two register buffers: the loads of the next batch are in flight while the
         // MFMAs of the current one run
-        load(0, kbA, ubA);
+        load(0, kbA, ubA, mA);
         for (int j0 = 0; j0 < nk; j0 += 2 * KB) {
-          load(j0 + KB, kbB, ubB);
-          mma(kbA, ubA);
+          load(j0 + KB, kbB, ubB, mB);
+          mma(kbA, ubA, mA);
           if (j0 + KB >= nk) break;
-          load(j0 + 2 * KB, kbA, ubA);
-          mma(kbB, ubB);
+          load(j0 + 2 * KB, kbA, ubA, mA);
+          mma(kbB, ubB, mB);
         }
       }
     }
@@ -566,6 +571,7 @@ int32_t launch_update(const cbs_system* s, int32_t nruns, void* r, const void* q
   a.count = count;
   a.grp_off = s->proj.grp_off;
   a.grp_key = s->proj.grp_key;
+  a.grp_mask = s->proj.grp_mask;
   a.grp_u = std::is_same<R, double>::value ? (const R*)s->proj.grp_u64 : (const R*)s->proj.grp_u32;
   const int grid = (a.nlogical + 7) / 8 * 8;
   if (std::is_same<R, float>::value && lo_arith_fp32())

@@ -168,15 +168,18 @@ static int32_t build_projectors(cbs_system* s, const cbs_proj* pr) {
   std::vector<int32_t>& grp_off = gt.grp_off;
   std::vector<int32_t>& grp_key = gt.grp_key;
   std::vector<double>& grp_u = gt.grp_u;
+  std::vector<int32_t>& grp_mask = gt.grp_mask;
   const int64_t ngroups = (int64_t)grp_off.size() - 1;
   P.grp_nkeys = (int64_t)grp_off[ngroups];
   if (grp_key.empty()) {   // keep the device pointers valid
     grp_key.push_back(0);
+    grp_mask.push_back(0);
     grp_u.resize(KG * 4, 0.0);
   }
   std::vector<float> grp_u32(grp_u.begin(), grp_u.end());
   CBS_TRY(upload(grp_off, &P.grp_off));
   CBS_TRY(upload(grp_key, &P.grp_key));
+  CBS_TRY(upload(grp_mask, &P.grp_mask));
   CBS_TRY(upload(grp_u, &P.grp_u64));
   CBS_TRY(upload(grp_u32, &P.grp_u32));
   std::vector<float> u32(u64.begin(), u64.end()), ptu32(pt_u.begin(), pt_u.end()),
@@ -215,6 +218,7 @@ static void free_system(cbs_system* s) {
   f(P.pt_u32);
   f(P.grp_off);
   f(P.grp_key);
+  f(P.grp_mask);
   f(P.grp_u64);
   f(P.grp_u32);
   f(s->last.vecs);

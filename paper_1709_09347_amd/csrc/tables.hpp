@@ -7,7 +7,9 @@
 // Grouped ket table: points in groups of kg consecutive indices; group g uses the
 // keys [grp_off[g], grp_off[g+1]) (ascending) and, per key, the values of its kg points
 // (zero where the point is outside that ball; a ball wider than the transverse period
-// reaches a point twice with the same key, and the two values add).
+// reaches a point twice with the same key, and the two values add).  grp_mask holds per
+// key one bit per block of 16 points of the group: set where a value of the block is
+// nonzero (the matrix-core ket skips the other blocks).
 
 #pragma once
 
@@ -19,7 +21,7 @@
 namespace cbs {
 
 struct GroupTables {
-  std::vector<int32_t> grp_off, grp_key;
+  std::vector<int32_t> grp_off, grp_key, grp_mask;
   std::vector<double> grp_u;   // [key][kg][4]
 };
 
@@ -30,6 +32,7 @@ inline std::string build_group_tables(int64_t n_points, const std::vector<int32_
   const int64_t ngroups = (n_points + kg - 1) / kg;
   t.grp_off.assign(ngroups + 1, 0);
   t.grp_key.clear();
+  t.grp_mask.clear();
   t.grp_u.clear();
   for (int64_t g = 0; g < ngroups; ++g) {
     const int64_t n0 = g * kg, n1 = std::min<int64_t>(n0 + kg, n_points);
@@ -46,6 +49,11 @@ inline std::string build_group_tables(int64_t n_points, const std::vector<int32_
         const size_t k = k0 + (std::lower_bound(keys.begin(), keys.end(), pt_key[e]) - keys.begin());
         for (int i = 0; i < 4; ++i) t.grp_u[(k * kg + (n - n0)) * 4 + i] += pt_u[4 * (size_t)e + i];
       }
+    t.grp_mask.resize(t.grp_key.size(), 0);
+    for (size_t k = k0; k < t.grp_key.size(); ++k)
+      for (int p = 0; p < kg; ++p)
+        for (int i = 0; i < 4; ++i)
+          if (t.grp_u[(k * kg + p) * 4 + i] != 0.0) t.grp_mask[k] |= 1 << (p / 16);
     if (t.grp_key.size() >= ((size_t)1 << 31)) return "grouped projector table too large";
     t.grp_off[g + 1] = (int32_t)t.grp_key.size();
   }

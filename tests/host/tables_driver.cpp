@@ -1,7 +1,8 @@
 // Runs the host-side grouped-table builder on a binary input and writes its tables.
 // Input (little endian): int64 n_points, int32 kg, int64 nnz, int32 pt_off[n_points+1],
 // int32 pt_key[nnz], double pt_u[4*nnz].
-// Output: for each table, int64 length then the values (grp_off, grp_key, grp_u); on
+// Output: for each table, int64 length then the values (grp_off, grp_key, grp_u,
+// grp_mask); on
 // failure the reason on stderr, exit 2.
 #include <cstdio>
 #include <vector>
@@ -41,6 +42,7 @@ int main(int argc, char** argv) {
   wr(o, t.grp_off);
   wr(o, t.grp_key);
   wr(o, t.grp_u);
+  wr(o, t.grp_mask);
   fclose(o);
   return 0;
 }

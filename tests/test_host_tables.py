@@ -4,7 +4,8 @@ The builder (paper_1709_09347_amd/csrc/tables.hpp, plain C++) is compiled with g
 on the projector sets of the synthetic workloads.  Checked against the input entries:
 the groups cover the points in order, keys ascend within a group, and per point and key
 the grouped values equal the sum of the point's entries with that key (a ball wider than
-the 5x5 transverse cell reaches some points twice with the same key), zero elsewhere.
+the 5x5 transverse cell reaches some points twice with the same key), zero elsewhere;
+and the block mask marks exactly the 16-point blocks with a nonzero value.
 """
 import os
 import subprocess
@@ -57,7 +58,7 @@ def _run(driver, tmp_path, n, off, keys, vals, kg):
     subprocess.run([driver, str(inp), str(out)], check=True)
     data = open(out, "rb").read()
     tabs, pos = [], 0
-    for dt in (np.int32, np.int32, np.float64):
+    for dt in (np.int32, np.int32, np.float64, np.int32):
         m = int(np.frombuffer(data, np.int64, 1, pos)[0])
         pos += 8
         tabs.append(np.frombuffer(data, dt, m, pos).copy())
@@ -71,10 +72,14 @@ def test_grouped_ket_table(driver, tmp_path, case):
     kg = 64
     off, keys, vals, pts = _point_major(sysw)
     n = sysw.n
-    grp_off, grp_key, grp_u = _run(driver, tmp_path, n, off, keys, vals, kg)
+    grp_off, grp_key, grp_u, grp_mask = _run(driver, tmp_path, n, off, keys, vals, kg)
     ng = (n + kg - 1) // kg
     grp_u = grp_u.reshape(-1, kg, 4)
     assert len(grp_off) == ng + 1 and grp_off[0] == 0 and grp_off[-1] == len(grp_key)
+    # one bit per 16-point block of a group: set exactly where the block has a nonzero value
+    nz_blocks = np.any(grp_u.reshape(len(grp_key), kg // 16, 16 * 4) != 0, axis=2)
+    want_mask = (nz_blocks * (1 << np.arange(kg // 16))).sum(axis=1)
+    np.testing.assert_array_equal(grp_mask, want_mask)
     want = {}
     for e in range(len(keys)):
         k = (int(pts[e]), int(keys[e]))
