@@ -165,102 +165,110 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
   if (!__syncthreads_or(any)) return;
   // Every wave covers all 16 runs (four groups g of 4 runs: four independent MFMA chains
   // that share each table load) over every 4th step of 4 ball entries; the four waves'
-  // partial products are summed through LDS.
+  // partial products are summed through LDS.  The ball's entries come in three segments
+  // by cell shift w = -1, 0, +1; each segment is contracted without its Bloch phase, which
+  // multiplies the segment's complex sums afterwards (c += z^w c_w), so the inner loop
+  // holds no phase factors.
   __shared__ C red[4][4][16][4];
+  __shared__ cplx<C> cw[16][2][4];
   const int row = lane & 15, kslot = lane >> 4, col = lane & 15;
   const int half = (row >> 1) & 1, reim = row & 1;
-  const cplx<R>* vrow[4];
-  cplx<C> zp[4], zm[4];
+  // lane's component of the gathered vector: run (row >> 2) of group g, primal or dual
+  // (half), real or imaginary part (reim); entry idx is at vrow[g][4 * idx]
+  const R* vrow[4];
   bool rvalid[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     const int run = srun[4 * g + (row >> 2)];
     rvalid[g] = run >= 0;
-    zp[g] = rvalid[g] ? ccast<C, double>(a.coef[run].c[3 * half + 1]) : mkc<C>(0, 0);
-    zm[g] = rvalid[g] ? ccast<C, double>(a.coef[run].c[3 * half + 2]) : mkc<C>(0, 0);
-    vrow[g] = reinterpret_cast<const cplx<R>*>(a.v + (int64_t)(rvalid[g] ? run : 0) * a.N) + half;
+    vrow[g] = reinterpret_cast<const R*>(a.v + (int64_t)(rvalid[g] ? run : 0) * a.N) + 2 * half + reim;
   }
-  const int s0 = a.seg[4 * atom], s1 = a.seg[4 * atom + 1], s2 = a.seg[4 * atom + 2], s3 = a.seg[4 * atom + 3];
-  typename mf4<C>::T acc[4];
+  if (tid < 128) (&cs[0][0][0])[tid] = mkc<C>(0, 0);
+  for (int sg = 0; sg < 3; ++sg) {
+    const int sa = a.seg[4 * atom + sg], sb = a.seg[4 * atom + sg + 1];
+    if (sa == sb) continue;   // uniform over the workgroup
+    typename mf4<C>::T acc[4];
 #pragma unroll
-  for (int g = 0; g < 4; ++g) acc[g] = {0, 0, 0, 0};
-  // FP64 arithmetic: the table entries (point index, projector value) of the next step
-  // of 4 ball entries are loaded while the gathers of this step are in flight, so each
-  // step waits for one memory latency rather than for the table load and then the gather
-  // that depends on it.  (With FP32 arithmetic the plain loop is faster: more waves fit.)
-  if constexpr (sizeof(C) == 8) {
-    const int e_first = s0 + 4 * wv + kslot;
-    int idx0 = 0;
-    C bv0 = 0;
-    if (e_first < s3) {
-      idx0 = a.idx[e_first];
-      if (col < 4) bv0 = (C)a.u[4 * (int64_t)e_first + col];
+    for (int g = 0; g < 4; ++g) acc[g] = {0, 0, 0, 0};
+    if constexpr (sizeof(C) == 8) {
+      // FP64 arithmetic: the table entries (point index, projector value) of the next
+      // step are loaded while the gathers of this step are in flight, so each step waits
+      // for one memory latency rather than for the table load and then the gather that
+      // depends on it.  (With FP32 arithmetic the plain loop is faster: more waves fit.)
+      // Loads are unconditional (indices clamped into the segment), so the waits count
+      // only the gathers and leave the next step's loads in flight.  Entries past the
+      // segment carry a zero projector value and rows of empty run slots are discarded,
+      // so the gathered values need no masking.
+      const int e_first = sa + 4 * wv + kslot;
+      const int el = min(e_first, sb - 1);
+      int idx0 = a.idx[el];
+      C bv0 = (e_first < sb && col < 4) ? (C)a.u[4 * (int64_t)el + (col & 3)] : (C)0;
+      for (int e = e_first; e - kslot < sb; e += 16) {
+        C vv[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) vv[g] = (C)vrow[g][4 * (int64_t)idx0];
+        const int e1 = e + 16;
+        const int e1l = min(e1, sb - 1);
+        const int idx1 = a.idx[e1l];
+        const C u1 = (C)a.u[4 * (int64_t)e1l + (col & 3)];
+        const C bv1 = (e1 < sb && col < 4) ? u1 : (C)0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[g] = mfma16x16x4(vv[g], bv0, acc[g]);
+        idx0 = idx1;
+        bv0 = bv1;
+      }
+    } else {
+      for (int e0 = sa + 4 * wv; e0 < sb; e0 += 16) {
+        const int e = e0 + kslot;
+        const bool ok = e < sb;
+        const int elc = min(e, sb - 1);
+        const int idx = a.idx[elc];
+        const C u = (C)a.u[4 * (int64_t)elc + (col & 3)];
+        const C bv = (ok && col < 4) ? u : (C)0;
+        C vv[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) vv[g] = (C)vrow[g][4 * (int64_t)idx];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[g] = mfma16x16x4(vv[g], bv, acc[g]);
+      }
     }
-    for (int e = e_first; e - kslot < s3; e += 16) {
-      cplx<C> vv[4];
+    // only the lanes of output columns 0..3 (the four projectors) carry results
+    if ((lane & 15) < 4) {
+      const int q = (lane >> 4) * 4 + (lane & 15);
 #pragma unroll
       for (int g = 0; g < 4; ++g)
-        vv[g] = (e < s3 && rvalid[g]) ? ccast<C, R>(vrow[g][2 * (int64_t)idx0]) : mkc<C>(0, 0);
-      const int e1 = e + 16;
-      int idx1 = 0;
-      C bv1 = 0;
-      if (e1 < s3) {
-        idx1 = a.idx[e1];
-        if (col < 4) bv1 = (C)a.u[4 * (int64_t)e1 + col];
-      }
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const cplx<C> p = (e < s1) ? cmul<C>(zm[g], vv[g]) : (e < s2) ? vv[g] : cmul<C>(zp[g], vv[g]);
-        acc[g] = mfma16x16x4(reim ? p.y : p.x, bv0, acc[g]);
-      }
-      idx0 = idx1;
-      bv0 = bv1;
+        for (int v = 0; v < 4; ++v) red[wv][g][q][v] = acc[g][v];
     }
-  } else {
-    for (int e0 = s0 + 4 * wv; e0 < s3; e0 += 16) {
-      const int e = e0 + kslot;
-      const bool ok = e < s3;
-      int idx = 0;
-      C bv = 0;
-      if (ok) {
-        idx = a.idx[e];
-        if (col < 4) bv = (C)a.u[4 * (int64_t)e + col];
-      }
-      cplx<C> vv[4];
+    __syncthreads();
+    {
+      // thread t < 256: group g = t/64 reduces lane t%64 over the four waves
+      const int g = tid >> 6, l2 = tid & 63;
+      if ((l2 & 15) < 4) {
+        const int q = (l2 >> 4) * 4 + (l2 & 15);
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
-        vv[g] = (ok && rvalid[g]) ? ccast<C, R>(vrow[g][2 * (int64_t)idx]) : mkc<C>(0, 0);
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const cplx<C> p = (e < s1) ? cmul<C>(zm[g], vv[g]) : (e < s2) ? vv[g] : cmul<C>(zp[g], vv[g]);
-        acc[g] = mfma16x16x4(reim ? p.y : p.x, bv, acc[g]);
+        for (int v = 0; v < 4; ++v) {
+          const C sum = red[0][g][q][v] + red[1][g][q][v] + red[2][g][q][v] + red[3][g][q][v];
+          const int r = mfma16_row<C>(l2, v);   // output row held by lane l2
+          C* dst = reinterpret_cast<C*>(&cw[4 * g + (r >> 2)][(r >> 1) & 1][l2 & 15]);
+          dst[r & 1] = sum;
+        }
       }
     }
-  }
-  // only the lanes of output columns 0..3 (the four projectors) carry results
-  if ((lane & 15) < 4) {
-    const int q = (lane >> 4) * 4 + (lane & 15);
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) red[wv][g][q][v] = acc[g][v];
-  }
-  __syncthreads();
-  {
-    // thread t < 256: group g = t/64 reduces lane t%64 over the four waves
-    const int g = tid >> 6, l2 = tid & 63;
-    if ((l2 & 15) < 4) {
-      const int q = (l2 >> 4) * 4 + (l2 & 15);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const C sum = red[0][g][q][v] + red[1][g][q][v] + red[2][g][q][v] + red[3][g][q][v];
-        const int r = mfma16_row<C>(l2, v);   // output row held by lane l2
-        C* dst = reinterpret_cast<C*>(&cs[4 * g + (r >> 2)][(r >> 1) & 1][l2 & 15]);
-        dst[r & 1] = sum;
+    __syncthreads();
+    if (tid < 128) {
+      // c[run][half][i] += z^w c_w: w = -1 -> 1/z (primal) or conj z (dual), +1 -> z or 1/conj z
+      const int r2 = tid >> 3, h2 = (tid >> 2) & 1, i = tid & 3;
+      const int rr = srun[r2];
+      if (rr >= 0) {
+        const cplx<C> c = cw[r2][h2][i];
+        cplx<C> t = c;
+        if (sg != 1) t = cmul<C>(ccast<C, double>(a.coef[rr].c[3 * h2 + (sg == 0 ? 2 : 1)]), c);
+        cs[r2][h2][i] = cadd<C>(cs[r2][h2][i], t);
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
   const RunCoef* cfp = a.coef;
   for (int t = tid; t < 16 * 24; t += 256) {
     const int r2 = t / 24, rem = t - r2 * 24;
