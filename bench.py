@@ -4,15 +4,19 @@
 Workload: the 48x48x32 cell (h = 0.3 bohr, 8th-order finite differences) with 96
 pseudo-atoms on a cylinder of radius 6 bohr (Gaussian local potential plus four
 Gaussian-supported projectors each), E = 0.2 Ha, annulus 0.5 < |lambda| < 2,
-N_q = 32 nodes per circle, L = 16 right-hand sides, M = 8 moments, every linear
-solve to a 1e-10 relative residual.  Inputs are seeded and synthetic and resident
-in device memory before the timed region.
+N_q = 32 nodes per circle, L = 16 real random right-hand sides, M = 8 moments, every
+linear solve to a 1e-10 relative residual.  Inputs are seeded and synthetic and
+resident in device memory before the timed region.
 
-One step = one complete solve at one energy (BiCG with duals at all nodes, moments,
-Hankel SVD, Rayleigh-Ritz extraction, residuals).  The mixed-precision path (complex128
-BiCG until a run's residual is below 1e-5, then complex64 vectors and FP32 operator
-applications with complex128 residual replacement) is the reported value; the
-complex128 path is timed beside it on the same inputs.
+One step = one complete solve at one energy (BiCG with duals at the nodes, moments,
+Hankel SVD, Rayleigh-Ritz extraction, residuals).  The blocks are real and so is V, so
+the solutions at the mirrored nodes conj z_j are the conjugates of those at z_j: 16 of
+the 32 nodes per circle are solved (256 runs of a system and its dual) and the moments
+sum the mirrored pairs.  The mixed-precision path (complex128 BiCG until a run's
+residual is below 1e-6, then complex64 vectors and FP32 operator applications with
+complex128 residual replacement) is the reported value; the complex128 path is timed
+beside it on the same inputs, and the mixed path with complex random V (every node
+solved, 512 runs) is timed after them.
 
 The JSON line also carries the roofline of the dominant kernel (the BiCG stencil,
 timed per launch with HIP events on the stream it runs on in a diagnostic solve
@@ -65,8 +69,8 @@ def cpu_baseline(sysw, E, V, iters_per_run, n_runs, budget_s=12.0):
         "kind": "oracle",
         "sample": (f"{done} BiCG iterations (primal+dual) of one run on the oracle's scipy.sparse "
                    f"operator at this workload ({t_used:.1f} s, 1 thread), extrapolated to {n_runs} runs "
-                   f"x {iters_per_run:.0f} iterations (the GPU FP64 solve's mean); moments and "
-                   f"extraction not included"),
+                   f"x {iters_per_run:.0f} iterations (the GPU FP64 solve's mean; the oracle solves "
+                   f"every node); moments and extraction not included"),
     }
 
 
@@ -76,7 +80,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", choices=("both", "fp64", "mixed"), default="both",
+    ap.add_argument("--legs", choices=("both", "fp64", "mixed", "mixed_complex_rhs"), default="both",
                     help="time one precision only (profiling); the JSON line needs both")
     ap.add_argument("--iters-cap", type=int, default=0,
                     help="cap BiCG at this many iterations (short runs for counter collection; "
@@ -111,30 +115,37 @@ def main():
     sysw = w.systems[0]
     E = w.solve.energies[0]
     L, M = w.solve.n_rhs, w.solve.n_mom
-    Vh = W.make_rhs(sysw.n, L, w.seed_rhs)
+    Vh = W.make_rhs(sysw.n, L, w.seed_rhs, real=True)
     s = cbs.System.from_workload(sysw)
     V = torch.from_numpy(Vh).to(dev)
+    Vz = torch.from_numpy(W.make_rhs(sysw.n, L, w.seed_rhs)).to(dev)   # complex V: every node
     torch.cuda.synchronize()
 
     runs = {}
-    legs = [(n, p) for n, p in (("fp64", cbs.CBS_FP64), ("mixed", cbs.CBS_MIXED))
-            if args.legs in ("both", n)]
-    for name, prec in legs:
+    if args.legs != "both":
+        names = (args.legs,)
+    elif args.iters_cap > 0:
+        names = ("fp64", "mixed")
+    else:
+        names = ("fp64", "mixed", "mixed_complex_rhs")
+    legs = [(n, p, v) for n, p, v in (("fp64", cbs.CBS_FP64, V), ("mixed", cbs.CBS_MIXED, V),
+                                      ("mixed_complex_rhs", cbs.CBS_MIXED, Vz)) if n in names]
+    for name, prec, Vl in legs:
         prm = cbs.default_params(n_rhs=L, n_mom=M, precision=prec)
         if args.iters_cap > 0:
             prm.max_iter = args.iters_cap
         for _ in range(args.warmup):
-            s.solve(E, V, prm, want_vectors=False)
+            s.solve(E, Vl, prm, want_vectors=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            lam, _, res, info, rc = s.solve(E, V, prm, want_vectors=False)
+            lam, _, res, info, rc = s.solve(E, Vl, prm, want_vectors=False)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         runs[name] = dict(t=dt, lam=lam, res=res, info=info, rc=rc)
-        print(f"# {name}: {dt:.3f} s/energy, {len(lam)} eigenvalues, rank {info.rank}, BiCG iters "
-              f"max {info.iters_max} mean {info.iters_mean:.1f}, max solve residual "
-              f"{info.max_solve_resid:.2e}, max eigen residual {info.max_eig_resid:.2e}, rc {rc}",
+        print(f"# {name}: {dt:.3f} s/energy, {len(lam)} eigenvalues, rank {info.rank}, nodes solved "
+              f"{info.nodes_solved}, BiCG iters max {info.iters_max} mean {info.iters_mean:.1f}, max solve "
+              f"residual {info.max_solve_resid:.2e}, max eigen residual {info.max_eig_resid:.2e}, rc {rc}",
               file=sys.stderr, flush=True)
 
     ty64, ty32, tune_log = s.tiling()
@@ -182,10 +193,15 @@ def main():
         "dtype": "c64+c128",
         "data": "synthetic",
         "config": {"workload": "48x48x32 h=0.3 fd8, 96 atoms x 4 projectors, E=0.2 Ha, N_q=32, "
-                               "L=16, M=8, BiCG to 1e-10",
-                   "global_batch": 32 * L, "seq_len": sysw.n, "parallelism": "none"},
+                               "L=16 real random V (16 of 32 nodes per circle solved, the mirrored "
+                               "ones by conjugation), M=8, BiCG to 1e-10",
+                   "global_batch": mixed["info"].nodes_solved * L, "seq_len": sysw.n,
+                   "parallelism": "none"},
         "fp64_s_per_energy": round(fp64["t"], 4),
         "speedup_mixed_vs_fp64": round(fp64["t"] / mixed["t"], 3),
+        "mixed_complex_rhs_s_per_energy": round(runs["mixed_complex_rhs"]["t"], 4),
+        "nodes_solved": {"real_rhs": mixed["info"].nodes_solved,
+                         "complex_rhs": runs["mixed_complex_rhs"]["info"].nodes_solved},
         "n_eigs": int(len(mixed["lam"])),
         "lambda_rel_diff_mixed_vs_fp64": dl,
         "max_eig_resid": float(max(mixed["info"].max_eig_resid, fp64["info"].max_eig_resid)),

@@ -105,10 +105,16 @@ typedef struct {
                            with FP64 residual replacement (iterative refinement) to tol */
   int32_t extraction;   /* CBS_RR (default) or CBS_HANKEL */
   int32_t half_stop;    /* 1: stop all solves once more than half of the nodes converged (Sec. 3.3) */
-  double inner_tol;     /* CBS_MIXED: residual below which a run continues in complex64 (1e-5) */
+  double inner_tol;     /* CBS_MIXED: residual below which a run continues in complex64 (1e-6) */
   int32_t max_refine;   /* cap on FP64 residual replacements per run (60) */
   int32_t chunk;        /* iterations per captured graph between convergence polls (even) */
   int32_t profile;      /* 1: no graph; HIP events time every BiCG stencil launch (cbs_info.stencil_*) */
+  int32_t conj_nodes;   /* 1 (default): when every right-hand side is real (imaginary parts exactly
+                           zero), solve only the nodes with 0 < theta_j < pi.  The blocks H0, H+, H-
+                           are real, so P(conj z) = conj P(z): the solutions at the mirrored nodes
+                           conj z_j are the complex conjugates, and each mirrored pair adds
+                           2 Re(w z^k y) to the moments (Sec. 3.1 Eq. 7 summed in pairs).  Same
+                           result, half the linear solves.  0: solve every node. */
 } cbs_params;
 
 /* Per-solve diagnostics. */
@@ -134,6 +140,7 @@ typedef struct {
   int64_t stencil_lo_launches;
   double stencil_lo_ms;
   double stencil_lo_bytes;
+  int32_t nodes_solved;     /* nodes per circle whose systems were solved: n_q, or n_q/2 with conj_nodes */
 } cbs_info;
 
 /* ---- errors ---------------------------------------------------------- */

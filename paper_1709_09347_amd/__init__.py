@@ -55,7 +55,8 @@ class Params(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("extraction", ctypes.c_int32), ("half_stop", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("conj_nodes", ctypes.c_int32)]
 
     def __repr__(self):
         return "Params(" + ", ".join(f"{n}={getattr(self, n)}" for n, _ in self._fields_) + ")"
@@ -70,7 +71,8 @@ class Info(ctypes.Structure):
                 ("t_extract_ms", ctypes.c_double), ("matvecs", ctypes.c_int64),
                 ("stencil_launches", ctypes.c_int64), ("stencil_ms", ctypes.c_double),
                 ("stencil_bytes", ctypes.c_double), ("stencil_lo_launches", ctypes.c_int64),
-                ("stencil_lo_ms", ctypes.c_double), ("stencil_lo_bytes", ctypes.c_double)]
+                ("stencil_lo_ms", ctypes.c_double), ("stencil_lo_bytes", ctypes.c_double),
+                ("nodes_solved", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

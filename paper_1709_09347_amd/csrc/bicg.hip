@@ -975,7 +975,8 @@ int32_t check_params(const cbs_params* p, bool need_moments) {
   }
   if (!(p->lambda_min > 0 && p->lambda_min < 1) || p->n_q < 1 || p->n_rhs < 1 || !(p->tol > 0) || p->max_iter < 1 ||
       (p->precision != CBS_FP64 && p->precision != CBS_MIXED) ||
-      (p->precision == CBS_MIXED && !(p->inner_tol > 0 && p->inner_tol < 1))) {
+      (p->precision == CBS_MIXED && !(p->inner_tol > 0 && p->inner_tol < 1)) ||
+      (p->conj_nodes != 0 && p->conj_nodes != 1)) {
     set_error("invalid solver parameters");
     return CBS_EINVAL;
   }

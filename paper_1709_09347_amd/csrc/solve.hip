@@ -46,11 +46,14 @@ static void quadrature(double lmin, int n_q, std::vector<c64>& z1, std::vector<c
   }
 }
 
-// S[k][l][n] for k in [k0, k0+nk): coefficient tables ca[j][k] = w1 z1^k, cb[j][k] = w2 z2^k.
+// S[k][l][n] for k in [k0, k0+nk): coefficient tables ca[j][k] = w1 z1^k, cb[j][k] = w2 z2^k,
+// over the n_q solved nodes; with conj, each solved node stands for itself and its mirror
+// conj z_j (real right-hand sides and real blocks: the mirror's solution is conj y and its
+// weight conj w), so the pair adds t + conj t = 2 Re t.
 constexpr int MOM_CHUNK = 8;
-__global__ void __launch_bounds__(256) k_moments(int64_t N, int32_t L, int32_t n_q, int32_t nk_total, int32_t k0,
-                                                 int32_t nk, const Pair<double>* Y, const c64* ca, const c64* cb,
-                                                 c64* S) {
+__global__ void __launch_bounds__(256) k_moments(int64_t N, int32_t L, int32_t n_q, int32_t conj, int32_t nk_total,
+                                                 int32_t k0, int32_t nk, const Pair<double>* Y, const c64* ca,
+                                                 const c64* cb, c64* S) {
   const int64_t total = N * L;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t l = g / N, n = g - l * N;
@@ -69,8 +72,39 @@ __global__ void __launch_bounds__(256) k_moments(int64_t N, int32_t L, int32_t n
     }
 #pragma unroll
     for (int k = 0; k < MOM_CHUNK; ++k)
-      if (k < nk) S[((int64_t)(k0 + k) * L + l) * N + n] = acc[k];
+      if (k < nk) S[((int64_t)(k0 + k) * L + l) * N + n] = conj ? make_double2(2.0 * acc[k].x, 0.0) : acc[k];
   }
+}
+
+// flag[0] = 1 if any imaginary part of the n values is nonzero (or NaN)
+__global__ void __launch_bounds__(256) k_any_imag(int64_t n, const c64* v, int32_t* flag) {
+  bool any = false;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
+    any = any || !(v[g].y == 0.0);
+  if (any) flag[0] = 1;
+}
+
+__global__ void k_clear_flag(int32_t* flag) { flag[0] = 0; }
+
+static int32_t launch_grid(int64_t work);
+
+// Quadrature nodes per circle to solve: half of them (0 < theta < pi) when the mirrored
+// nodes can be taken from conjugation (conj_nodes, even n_q, every right-hand side real).
+static int32_t nodes_to_solve(cbs_system* s, const cbs_params* prm, const c64* const* V, int n_v, int64_t count,
+                              hipStream_t st, int32_t* nq_solved) {
+  *nq_solved = prm->n_q;
+  if (!prm->conj_nodes || prm->n_q % 2 != 0) return CBS_OK;
+  int32_t* flag = nullptr;
+  CBS_TRY(ws_get(s->ws, "rhs.imag", 1, &flag));
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, st, flag);
+  for (int i = 0; i < n_v; ++i)
+    hipLaunchKernelGGL(k_any_imag, dim3(launch_grid(count)), dim3(256), 0, st, count, V[i], flag);
+  CBS_HIP(hipGetLastError());
+  int32_t h = 1;
+  CBS_HIP(hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CBS_HIP(hipStreamSynchronize(st));
+  if (h == 0) *nq_solved = prm->n_q / 2;
+  return CBS_OK;
 }
 
 // Block Hankel matrices from mu (C[a + (k L + b) L] = mu_k[a][b]).
@@ -216,13 +250,14 @@ struct Extracted {
 
 // Steps 2-5 for one system / energy; Y = node solutions (pairs, run = j*L + l).
 int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, const Pair<double>* Y,
-                hipStream_t st, Extracted& out, double* t_mom_ms) {
-  const int L = prm->n_rhs, M = prm->n_mom, nq = prm->n_q, nk = 2 * M, n = L * M;
+                int32_t nq_solved, hipStream_t st, Extracted& out, double* t_mom_ms) {
+  const int L = prm->n_rhs, M = prm->n_mom, nq = nq_solved, nk = 2 * M, n = L * M;
+  const int32_t conj = nq_solved != prm->n_q;
   const int64_t N = s->N;
   Workspace& ws = s->ws;
   auto t0 = std::chrono::steady_clock::now();
   std::vector<c64> z1, w1, z2, w2;
-  quadrature(prm->lambda_min, nq, z1, w1, z2, w2);
+  quadrature(prm->lambda_min, prm->n_q, z1, w1, z2, w2);
   std::vector<c64> ca((size_t)nq * nk), cb((size_t)nq * nk);
   for (int j = 0; j < nq; ++j) {
     c64 pa = w1[j], pb = w2[j];
@@ -241,7 +276,7 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
   CBS_HIP(hipMemcpyAsync(dca, ca.data(), ca.size() * sizeof(c64), hipMemcpyHostToDevice, st));
   CBS_HIP(hipMemcpyAsync(dcb, cb.data(), cb.size() * sizeof(c64), hipMemcpyHostToDevice, st));
   for (int k0 = 0; k0 < nk; k0 += MOM_CHUNK) {
-    hipLaunchKernelGGL(k_moments, dim3(launch_grid(N * L)), dim3(256), 0, st, N, L, nq, nk, k0,
+    hipLaunchKernelGGL(k_moments, dim3(launch_grid(N * L)), dim3(256), 0, st, N, L, nq, conj, nk, k0,
                        std::min(MOM_CHUNK, nk - k0), Y, (const c64*)dca, (const c64*)dcb, S);
     CBS_HIP(hipGetLastError());
   }
@@ -517,12 +552,15 @@ extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, con
   hipStream_t st = (hipStream_t)stream;
   std::vector<c64> z1, w1, z2, w2;
   quadrature(prm->lambda_min, prm->n_q, z1, w1, z2, w2);
+  const c64* Vc = (const c64*)V;
+  int32_t nqs = prm->n_q;
+  CBS_TRY(nodes_to_solve(s, prm, &Vc, 1, (int64_t)prm->n_rhs * s->N, st, &nqs));
   NodeSolve ns;
-  CBS_TRY(solve_nodes(s, E, z1.data(), prm->n_q, prm->n_rhs, (const c64*)V, prm, st, ns));
+  CBS_TRY(solve_nodes(s, E, z1.data(), nqs, prm->n_rhs, Vc, prm, st, ns));
   Extracted ex;
   double tmom = 0;
   auto t0 = std::chrono::steady_clock::now();
-  CBS_TRY(extract(s, E, prm, (const c64*)V, ns.Y, st, ex, &tmom));
+  CBS_TRY(extract(s, E, prm, Vc, ns.Y, nqs, st, ex, &tmom));
   auto t1 = std::chrono::steady_clock::now();
   CBS_TRY(store_last(s, E, ex, st));
   const int cnt = (int)ex.lam.size();
@@ -560,6 +598,7 @@ extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, con
     info->stencil_lo_launches = ns.prof_lo_launches;
     info->stencil_lo_ms = ns.prof_lo_ms;
     info->stencil_lo_bytes = ns.prof_lo_bytes;
+    info->nodes_solved = nqs;
   }
   if (cnt > max_eigs) {
     set_error("cbs_solve: %d eigenvalues, output holds %d", cnt, max_eigs);
@@ -611,8 +650,17 @@ extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, 
   }
   CBS_HIP(hipSetDevice(systems[0]->device));
   hipStream_t st = (hipStream_t)stream;
-  const int L = prm->n_rhs, nq = prm->n_q;
+  const int L = prm->n_rhs;
   const bool mixed = prm->precision == CBS_MIXED;
+  // conjugate nodes only when every system's right-hand sides are real
+  bool halve = true;
+  for (int s = 0; s < n_sys; ++s) {
+    int32_t q = prm->n_q;
+    const c64* Vs = (const c64*)V[s];
+    CBS_TRY(nodes_to_solve(systems[s], prm, &Vs, 1, (int64_t)L * systems[s]->N, st, &q));
+    halve = halve && q != prm->n_q;
+  }
+  const int nq = halve ? prm->n_q / 2 : prm->n_q;
   // memory per energy for all systems
   const double per_pt = mixed ? (5 * 16 + 5 * 32 + 32) : (5 * 32 + 32);
   double per_energy = 0;
@@ -626,7 +674,7 @@ extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, 
   }
   const int wave = std::max(1, std::min(n_E, (int)(budget / per_energy)));
   std::vector<c64> z1, w1, z2, w2;
-  quadrature(prm->lambda_min, nq, z1, w1, z2, w2);
+  quadrature(prm->lambda_min, prm->n_q, z1, w1, z2, w2);
   int32_t worst = CBS_OK;
   auto note = [&](int32_t rc) {
     if (rc != CBS_OK && (worst == CBS_OK || rc == CBS_EBREAKDOWN)) worst = rc;
@@ -670,7 +718,7 @@ extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, 
         double tmom = 0;
         auto t0 = std::chrono::steady_clock::now();
         const Pair<double>* Ye = ns.Y + (size_t)e * nq * L * sy->N;
-        int32_t rc = extract(sy, E[e0 + e], prm, (const c64*)V[s], Ye, st, ex, &tmom);
+        int32_t rc = extract(sy, E[e0 + e], prm, (const c64*)V[s], Ye, nq, st, ex, &tmom);
         if (rc != CBS_OK) return rc;
         auto t1 = std::chrono::steady_clock::now();
         CBS_TRY(store_last(sy, E[e0 + e], ex, st));
@@ -702,6 +750,7 @@ extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, 
           in.t_extract_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() - tmom;
           in.matvecs = (int64_t)(2 * sum);
           in.refine_steps = ns.n_ru;
+          in.nodes_solved = nq;
         }
         if (cnt > max_eigs) {
           note(CBS_ETOOMANY);

@@ -352,9 +352,10 @@ void cbs_params_default(cbs_params* p) {
   p->precision = CBS_FP64;
   p->extraction = CBS_RR;
   p->half_stop = 0;
-  p->inner_tol = 1e-5;
+  p->inner_tol = 1e-6;
   p->max_refine = 60;
   p->chunk = 8;
+  p->conj_nodes = 1;
 }
 
 int32_t cbs_system_create(cbs_system** out, int32_t device, const cbs_grid* g, const double* v_loc,

@@ -31,6 +31,30 @@ def test_batched_equals_single_solves(cuda):
             assert qep.match_sets(got, single) <= 1e-10
 
 
+def test_batched_real_sources_mirrored_nodes(cuda):
+    # real V on every system: the batch solves half the nodes; results equal the oracle and
+    # the single solves of every node
+    import torch
+    import paper_1709_09347_amd as cbs
+    systems = [W.tiny(with_proj=True, fd_order=8), W.config(1).systems[0]]
+    energies = [0.5, 4.0]
+    L = 8
+    hs = [cbs.System.from_workload(s) for s in systems]
+    Vs = [torch.from_numpy(W.make_rhs(s.n, L, 17 + i, real=True)).to(cuda) for i, s in enumerate(systems)]
+    prm = cbs.default_params(n_rhs=L, n_mom=8)
+    lam_b, infos, rc = cbs.solve_batched(hs, energies, Vs, prm)
+    assert rc == 0 and all(i.nodes_solved == 16 for i in infos)
+    full = cbs.default_params(n_rhs=L, n_mom=8, conj_nodes=0)
+    for si, s in enumerate(systems):
+        h0, hp, hm = ham.build(s).blocks_dense()
+        for ei, E in enumerate(energies):
+            ref = qep.solve_dense(h0, hp, hm, E, 0.5, left=False).lam
+            got = lam_b[si][ei]
+            assert len(got) == len(ref) and qep.match_sets(got, ref) <= 1e-8
+            single, _, _, info1, _ = hs[si].solve(E, Vs[si], full, want_vectors=False)
+            assert info1.nodes_solved == 32 and qep.match_sets(got, single) <= 1e-10
+
+
 def test_batched_cfg3_systems_two_energies(cuda):
     # the four uneven grids of the batching workload, two energies of its range in one
     # batched pass (4 x 2 x 512 runs); BiCG needs ~750-1200 iterations at the low end of

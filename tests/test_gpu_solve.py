@@ -21,15 +21,16 @@ pytestmark = pytest.mark.gpu
 REFINED = 1e-12   # solve tolerance for the 1e-10 eigenpair-residual bar
 
 
-def _gpu_solve(sysw, E, cuda, L=8, M=8, seed=3, **kw):
+def _gpu_solve(sysw, E, cuda, L=8, M=8, seed=3, real_v=False, **kw):
     import torch
     import paper_1709_09347_amd as cbs
     s = cbs.System.from_workload(sysw)
-    V = torch.from_numpy(W.make_rhs(sysw.n, L, seed)).to(cuda)
+    V = torch.from_numpy(W.make_rhs(sysw.n, L, seed, real=real_v)).to(cuda)
     kw.setdefault("tol", REFINED)
     prm = cbs.default_params(n_rhs=L, n_mom=M, **kw)
     lam, vecs, res, info, rc = s.solve(E, V, prm)
-    print(f"{sysw.name} E={E} prec={prm.precision} ext={prm.extraction}: {len(lam)} eigs, rank {info.rank}, "
+    print(f"{sysw.name} E={E} prec={prm.precision} ext={prm.extraction} nodes {info.nodes_solved}: "
+          f"{len(lam)} eigs, rank {info.rank}, "
           f"iters {info.iters_max}, solve {info.t_solve_ms:.1f} ms, moments {info.t_moments_ms:.1f} ms, "
           f"extract {info.t_extract_ms:.1f} ms, max res {res.max() if len(res) else 0:.1e}")
     return lam, (vecs.cpu().numpy() if vecs is not None else None), res, info, rc
@@ -62,6 +63,29 @@ def test_solve_tiny_with_projectors(cuda, tiny_ref, precision):
     sysw, H, ref = tiny_ref
     lam, vecs, res, info, rc = _gpu_solve(sysw, 4.0, cuda, precision=precision)
     assert rc == 0
+    assert info.nodes_solved == 32   # complex right-hand sides: every node
+    _check_against(ref.lam, lam, vecs, res, H, 4.0, ref_vecs=ref.x)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_tiny_real_sources_mirrored_nodes(cuda, tiny_ref, precision):
+    # real V: half the nodes solved, the mirrored ones taken by conjugation; the result
+    # matches the oracle and the solve of every node with the same V
+    sysw, H, ref = tiny_ref
+    lam, vecs, res, info, rc = _gpu_solve(sysw, 4.0, cuda, precision=precision, real_v=True)
+    assert rc == 0 and info.nodes_solved == 16
+    _check_against(ref.lam, lam, vecs, res, H, 4.0, ref_vecs=ref.x)
+    lam_all, _, _, info_all, rc_all = _gpu_solve(sysw, 4.0, cuda, precision=precision, real_v=True, conj_nodes=0)
+    assert rc_all == 0 and info_all.nodes_solved == 32
+    assert len(lam_all) == len(lam) and qep.match_sets(lam, lam_all) <= 1e-10
+
+
+def test_mixed_precision_enters_the_complex64_phase(cuda, tiny_ref):
+    # profile mode counts the stencil launches of each phase: the mixed solve must run
+    # complex64 iterations (and complex128 ones before narrowing) and still meet the bars
+    sysw, H, ref = tiny_ref
+    lam, vecs, res, info, rc = _gpu_solve(sysw, 4.0, cuda, precision=1, profile=1)
+    assert rc == 0 and info.stencil_launches > 0 and info.stencil_lo_launches > 0
     _check_against(ref.lam, lam, vecs, res, H, 4.0, ref_vecs=ref.x)
 
 
@@ -137,5 +161,20 @@ def test_solve_cfg2_full_size_invariants(cuda, precision):
     assert rc == 0 and len(lam) > 0 and info.max_solve_resid <= REFINED
     assert qep.match_sets(lam, 1 / np.conj(lam)) <= 1e-8
     assert qep.match_sets(lam, np.conj(lam)) <= 1e-8
+    for i, l in enumerate(lam):
+        assert np.linalg.norm(H.apply(l, vecs[i], 0.2)) <= 1e-10
+
+
+def test_solve_cfg2_full_size_real_sources(cuda):
+    # the bench configuration: real V, mixed precision, mirrored nodes; the eigenvalues equal
+    # those of complex V solved at every node in complex128, and the invariants hold
+    sysw = W.config(2).systems[0]
+    H = ham.build(sysw)
+    lam, vecs, res, info, rc = _gpu_solve(sysw, 0.2, cuda, L=16, M=8, precision=1, seed=3002, real_v=True)
+    assert rc == 0 and info.nodes_solved == 16 and info.max_solve_resid <= REFINED
+    ref, _, _, info_ref, rc_ref = _gpu_solve(sysw, 0.2, cuda, L=16, M=8, precision=0, seed=3002)
+    assert rc_ref == 0 and info_ref.nodes_solved == 32
+    assert len(lam) == len(ref) > 0 and qep.match_sets(lam, ref) <= 1e-8
+    assert qep.match_sets(lam, 1 / np.conj(lam)) <= 1e-8
     for i, l in enumerate(lam):
         assert np.linalg.norm(H.apply(l, vecs[i], 0.2)) <= 1e-10

@@ -131,3 +131,38 @@ def test_eigen_residual_follows_solve_tolerance(tol, bar):
     r = qep.residuals(h0, hp, hm, E, lam, psi)
     assert r.max() <= bar
     assert r.max() >= 1e-3 * bar   # the residual is set by the solves, not by rounding
+
+
+@pytest.mark.parametrize("real_v", [True, False])
+def test_mirrored_nodes_of_real_sources(real_v):
+    """The blocks are real, so P(conj z) = conj P(z).  With real V the solution at the
+    mirrored node conj z_j (node n_q-1-j, theta -> 2 pi - theta) is conj Y_j on both circles,
+    the moments S_k are real, and summing 2 Re(w z^k Y) over the nodes with 0 < theta < pi
+    gives S_k (what the device path does with conj_nodes).  With complex V the mirror
+    identity fails (the negative control)."""
+    sysw = W.tiny(with_proj=True, fd_order=4)
+    h0, hp, hm = ham.build(sysw).blocks_dense()
+    for b in (h0, hp, hm):
+        assert np.max(np.abs(np.imag(b))) == 0.0
+    E, nq, L = 4.0, 8, 2
+    rng = np.random.default_rng(5)
+    V = rng.standard_normal((sysw.n, L))
+    if not real_v:
+        V = V + 1j * rng.standard_normal((sysw.n, L))
+    z1, w1, z2, w2 = ss.quadrature(0.5, nq)
+    Y1 = [np.linalg.solve(qep.P_dense(h0, hp, hm, E, z), V) for z in z1]
+    Y2 = [np.linalg.solve(qep.P_dense(h0, hp, hm, E, z), V) for z in z2]
+    scale = max(np.max(np.abs(y)) for y in Y1 + Y2)
+    mirror_err = max(max(np.max(np.abs(Y[nq - 1 - j] - np.conj(Y[j]))) for j in range(nq)) for Y in (Y1, Y2))
+    np.testing.assert_allclose(z1[::-1], np.conj(z1), rtol=1e-15, atol=1e-15)
+    np.testing.assert_allclose(w1[::-1], np.conj(w1), rtol=1e-15, atol=1e-15)
+    S = ss.moments(Y1, Y2, z1, w1, z2, w2, 6)
+    if real_v:
+        assert mirror_err <= 1e-12 * scale
+        h = nq // 2
+        for k, sk in enumerate(S):
+            half = sum(w1[j] * z1[j] ** k * Y1[j] - w2[j] * z2[j] ** k * Y2[j] for j in range(h))
+            assert np.max(np.abs(sk.imag)) <= 1e-12 * np.max(np.abs(sk))
+            np.testing.assert_allclose(2 * half.real, sk.real, rtol=0, atol=1e-12 * np.max(np.abs(sk)))
+    else:
+        assert mirror_err > 1e-3 * scale

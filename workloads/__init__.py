@@ -216,10 +216,13 @@ def free_system(nx, ny, nz, h, fd_order) -> System:
                   np.zeros(0), None, f"free_{nx}x{ny}x{nz}")
 
 
-def make_rhs(n: int, n_rhs: int, seed: int) -> np.ndarray:
-    """Random right-hand sides V as an [L, N] complex128 array."""
+def make_rhs(n: int, n_rhs: int, seed: int, real: bool = False) -> np.ndarray:
+    """Random right-hand sides V as an [L, N] complex128 array: complex Gaussian entries, or
+    with real=True real Gaussian entries (stored as complex128 with zero imaginary parts)."""
     rng = np.random.default_rng(seed)
     a = rng.standard_normal((n_rhs, n))
+    if real:
+        return a.astype(np.complex128)
     b = rng.standard_normal((n_rhs, n))
     return (a + 1j * b) / math.sqrt(2.0)
 
