@@ -40,7 +40,7 @@ METRIC = "time per energy to 1e-10 residual (mixed vs FP64 GPU); stencil HBM GB/
 # FETCH_SIZE and WRITE_SIZE on full-batch dispatches of this workload, each scaled by what the
 # counter reads for a plain 1 GiB device copy (bench.py --copy-calibration); the commands and
 # raw figures are in profiles/stencil_fp64_48x48x32_counters.md.  None once the kernel changes.
-STENCIL_TRAFFIC_RATIO = 1.0341
+STENCIL_TRAFFIC_RATIO = 1.0329
 
 
 def cpu_baseline(sysw, E, V, iters_per_run, n_runs, budget_s=12.0):
