@@ -193,7 +193,9 @@ int32_t cbs_bicg(cbs_system* sys, double E, int32_t n_z, const double* z, int32_
                  int32_t* iters, double* relres, cbs_info* info, void* stream);
 
 /* ---- the whole method at one energy (Algorithm 1 on the ring contour) --
- * V: device [L][N] complex128 right-hand sides (L = params->n_rhs).
+ * V: device [L][N] complex128 right-hand sides (L = params->n_rhs); when every
+ * imaginary part is zero and params->conj_nodes is set, half of the nodes are
+ * solved and the mirrored ones taken by conjugation (cbs_info.nodes_solved).
  * lambda: host [2*max_eigs], resid: host [max_eigs] (may be NULL),
  * vecs: device [max_eigs][N] complex128 (may be NULL), unit 2-norm, largest
  * component real positive.  Eigenvalues are sorted by |ln|lambda||, then by
