@@ -203,16 +203,19 @@ int32_t tall_gemm(int64_t N, int32_t K, int32_t nc, const c64* A, int64_t lda, c
 // ------------------------------------------------------------------ single-workgroup helpers
 constexpr int SWG = 256;   // threads of the single-workgroup kernels
 
-__device__ double block_max(double v, double* sh) {
+template <int WG>
+__device__ double block_max_wg(double v, double* sh) {
   v = fmax(v, __shfl_xor(v, 1, 64));
   for (int o = 2; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   double r = sh[0];
-  for (int w = 1; w < SWG / 64; ++w) r = fmax(r, sh[w]);
+  for (int w = 1; w < WG / 64; ++w) r = fmax(r, sh[w]);
   __syncthreads();
   return r;
 }
+
+__device__ double block_max(double v, double* sh) { return block_max_wg<SWG>(v, sh); }
 
 __device__ double block_sum(double v, double* sh) {
   for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
@@ -226,32 +229,41 @@ __device__ double block_sum(double v, double* sh) {
 
 // ------------------------------------------------------------------ one-sided Jacobi SVD
 // A (n x n, lda) is overwritten by U*Sigma, V starts as the identity and becomes W with
-// A_in W = U Sigma.  Columns are paired round-robin; each round's n/2 disjoint pairs are
-// handled by groups of SWG/(n/2) threads.  Output: sigma sorted descending (perm gives
-// the source column of each sorted position), U columns normalised in place.
-__global__ void __launch_bounds__(SWG) k_jacobi_svd(int32_t n, c64* A, int32_t lda, c64* V, int32_t ldv,
+// A_in W = U Sigma.  Columns are paired round-robin (slot 0 fixed, the others rotating by
+// one per round, so the slot of every column follows from the round number); each round's
+// n/2 disjoint pairs are handled by groups of JWG/(n/2) threads.  Output: sigma sorted
+// descending (perm gives the source column of each sorted position), U columns normalised
+// in place.
+constexpr int JWG = 1024;
+__global__ void __launch_bounds__(JWG) k_jacobi_svd(int32_t n, c64* A, int32_t lda, c64* V, int32_t ldv,
                                                      double* sigma, int32_t* perm, int32_t max_sweeps) {
-  __shared__ double sh[SWG / 64];
-  __shared__ int order[512];
+  __shared__ double sh[JWG / 64];
   __shared__ double sflag;
   const int tid = threadIdx.x;
-  for (int t = tid; t < n * n; t += SWG) {
+  for (int t = tid; t < n * n; t += JWG) {
     const int i = t % n, j = t / n;
     V[i + (int64_t)j * ldv] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   const int m = (n + 1) / 2 * 2;   // even number of slots (a dummy column when n is odd)
-  for (int t = tid; t < m; t += SWG) order[t] = t;
   __syncthreads();
   const int npairs = m / 2;
   int gsize = 1;   // threads per pair: a power of two, so xor shuffles stay inside the group
-  while (gsize * 2 * npairs <= SWG && gsize < 64) gsize *= 2;
+  while (gsize * 2 * npairs <= JWG && gsize < 64) gsize *= 2;
+  // column in slot k after r rotations: slot 0 holds column 0, slot k >= 1 holds
+  // column 1 + ((k - 1 - r) mod (m - 1))
+  auto slot_col = [&](int k, int r) {
+    if (k == 0) return 0;
+    int c = (k - 1 - r) % (m - 1);
+    if (c < 0) c += m - 1;
+    return 1 + c;
+  };
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double offmax = 0;
     for (int round = 0; round < m - 1; ++round) {
-      // pairs of this round: (order[k], order[m-1-k])
-      for (int pidx = tid / gsize; pidx < npairs; pidx += SWG / gsize) {
+      // pairs of this round: (slot k, slot m-1-k)
+      for (int pidx = tid / gsize; pidx < npairs; pidx += JWG / gsize) {
         const int sub = tid % gsize;
-        int p = order[pidx], q = order[m - 1 - pidx];
+        int p = slot_col(pidx, round), q = slot_col(m - 1 - pidx, round);
         if (p > q) {
           const int t = p;
           p = q;
@@ -292,21 +304,14 @@ __global__ void __launch_bounds__(SWG) k_jacobi_svd(int32_t n, c64* A, int32_t l
         }
       }
       __syncthreads();
-      // rotate the tournament: keep order[0], shift the rest
-      if (tid == 0) {
-        const int last = order[m - 1];
-        for (int k = m - 1; k > 1; --k) order[k] = order[k - 1];
-        order[1] = last;
-      }
-      __syncthreads();
     }
-    const double om = block_max(offmax, sh);
+    const double om = block_max_wg<JWG>(offmax, sh);
     if (tid == 0) sflag = om;
     __syncthreads();
     if (sflag < 1e-13) break;
   }
   // column norms, sort descending (simple selection by rank)
-  for (int j = tid; j < n; j += SWG) {
+  for (int j = tid; j < n; j += JWG) {
     double s2 = 0;
     for (int i = 0; i < n; ++i) s2 += cabs2<double>(A[i + (int64_t)j * lda]);
     sigma[512 + j] = sqrt(s2);   // scratch area after the output
@@ -314,7 +319,7 @@ __global__ void __launch_bounds__(SWG) k_jacobi_svd(int32_t n, c64* A, int32_t l
   __syncthreads();
   // ranks under a strict total order (a non-finite norm counts as -1, ties by index), so
   // perm is a permutation of 0..n-1 whatever the values are
-  for (int j = tid; j < n; j += SWG) {
+  for (int j = tid; j < n; j += JWG) {
     const double sj0 = sigma[512 + j];
     const double sj = isfinite(sj0) ? sj0 : -1.0;
     int rank = 0;
@@ -326,10 +331,10 @@ __global__ void __launch_bounds__(SWG) k_jacobi_svd(int32_t n, c64* A, int32_t l
     perm[rank] = j;
   }
   __syncthreads();
-  for (int r = tid; r < n; r += SWG) sigma[r] = sigma[512 + perm[r]];
+  for (int r = tid; r < n; r += JWG) sigma[r] = sigma[512 + perm[r]];
   __syncthreads();
   // normalise U columns
-  for (int j = tid; j < n; j += SWG) {
+  for (int j = tid; j < n; j += JWG) {
     const double sj = sigma[512 + j];
     if (sj > 0)
       for (int i = 0; i < n; ++i) A[i + (int64_t)j * lda] = zscale(A[i + (int64_t)j * lda], 1.0 / sj);
@@ -609,7 +614,7 @@ int32_t svd(int32_t n, c64* A, int32_t lda, c64* V, int32_t ldv, double* sigma, 
     set_error("svd: order %d above 512", n);
     return CBS_EINVAL;
   }
-  hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(SWG), 0, st, n, A, lda, V, ldv, sigma, perm, 60);
+  hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(JWG), 0, st, n, A, lda, V, ldv, sigma, perm, 60);
   CBS_HIP(hipGetLastError());
   return CBS_OK;
 }
