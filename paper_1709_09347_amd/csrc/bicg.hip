@@ -104,36 +104,37 @@ __global__ void __launch_bounds__(256) k_partials(int64_t N, int32_t nchunks, in
 }
 
 // Residual replacement, first half: x += xcoef p (the pending update), y += x, x = 0.
-// Work items: (entry of the replacement list, chunk of points); runs of the other phase
-// are skipped.
+// Work items: (entry of the replacement list, chunk of points), taken grid-stride by a
+// bounded grid (the list is short); runs of the other phase are skipped.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ru_pre(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* list,
                                                 const int32_t* count, const int32_t* status, int32_t need,
                                                 const double2* xcoef, const Pair<T>* P, Pair<T>* X,
                                                 Pair<double>* Y) {
-  const int lb = remap_active(blockIdx.x, min(nlogical, *count * nchunks));
-  if (lb < 0) return;
-  const int slot = lb / nchunks, ch = lb - slot * nchunks;
-  const int run = list[slot];
-  if (status[run] != need) return;
-  const int64_t chunk = (N + nchunks - 1) / nchunks;
-  const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
-  const double2 xc = xcoef[run];
-  const cplx<T> xa = mkc<T>((T)xc.x, (T)xc.y), xb = cconj<T>(xa);
-  for (int64_t n = lo + threadIdx.x; n < hi; n += 256) {
-    const int64_t g = (int64_t)run * N + n;
-    Pair<T> x = X[g];
-    const Pair<T> p = P[g];
-    x.a = cfma<T>(x.a, xa, p.a);
-    x.b = cfma<T>(x.b, xb, p.b);
-    Pair<double> y = Y[g];
-    y.a = cadd<double>(y.a, ccast<double, T>(x.a));
-    y.b = cadd<double>(y.b, ccast<double, T>(x.b));
-    Y[g] = y;
-    Pair<T> z;
-    z.a = mkc<T>(0, 0);
-    z.b = z.a;
-    X[g] = z;
+  const int nl = min(nlogical, *count * nchunks);
+  for (int lb = blockIdx.x; lb < nl; lb += gridDim.x) {
+    const int slot = lb / nchunks, ch = lb - slot * nchunks;
+    const int run = list[slot];
+    if (status[run] != need) continue;
+    const int64_t chunk = (N + nchunks - 1) / nchunks;
+    const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
+    const double2 xc = xcoef[run];
+    const cplx<T> xa = mkc<T>((T)xc.x, (T)xc.y), xb = cconj<T>(xa);
+    for (int64_t n = lo + threadIdx.x; n < hi; n += 256) {
+      const int64_t g = (int64_t)run * N + n;
+      Pair<T> x = X[g];
+      const Pair<T> p = P[g];
+      x.a = cfma<T>(x.a, xa, p.a);
+      x.b = cfma<T>(x.b, xb, p.b);
+      Pair<double> y = Y[g];
+      y.a = cadd<double>(y.a, ccast<double, T>(x.a));
+      y.b = cadd<double>(y.b, ccast<double, T>(x.b));
+      Y[g] = y;
+      Pair<T> z;
+      z.a = mkc<T>(0, 0);
+      z.b = z.a;
+      X[g] = z;
+    }
   }
 }
 
@@ -141,7 +142,9 @@ __global__ void __launch_bounds__(256) k_ru_pre(int64_t N, int32_t nchunks, int3
 // part; the ket of the projectors is added over the grouped table, 64-point groups with
 // lane = point and the coefficients of each key read uniformly); written as the working
 // residual R (precision T) and, when R64 is given, also in complex128 (needed when the
-// run changes phase).  Work items: (entry of the replacement list, chunk of groups).
+// run changes phase).  Work items: (entry of the replacement list, chunk of groups), taken
+// grid-stride by a bounded grid; the chunks are fine (one 64-point group per wave), so a
+// few replaced runs spread over many workgroups.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* list,
                                                  const int32_t* count, int32_t L, int32_t n_atoms,
@@ -151,68 +154,70 @@ __global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int
                                                  const int32_t* grp_key, const double* grp_u, Pair<T>* R,
                                                  Pair<double>* R64, double* part) {
   __shared__ double red[4][4];
-  const int lb = remap_active(blockIdx.x, min(nlogical, *count * nchunks));
-  if (lb < 0) return;
-  const int slot = lb / nchunks, ch = lb - slot * nchunks;
-  const int run = __builtin_amdgcn_readfirstlane(list[slot]);
-  if (status[run] != need) return;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const double2* v = V + (int64_t)(run % L) * N;
-  const double2* vdual = Vd + (int64_t)(run % L) * N;
-  typedef const CBS_CONST_AS int32_t* cint_p;
-  typedef const CBS_CONST_AS Pair<double>* ckt_p;
-  const cint_p goff = (cint_p)grp_off;
-  const cint_p gkey = (cint_p)grp_key;
-  const int64_t ngroups = (N + KG - 1) / KG;
-  const int64_t gpc = (ngroups + nchunks - 1) / nchunks;
-  const int64_t g0 = ch * gpc;
-  const int64_t g1 = (g0 + gpc < ngroups) ? g0 + gpc : ngroups;
-  double s[4] = {0, 0, 0, 0};
-  for (int64_t g = g0 + wv; g < g1; g += 4) {
-    const int64_t n = g * KG + lane;
-    Pair<double> k;
-    k.a = make_double2(0, 0);
-    k.b = k.a;
-    if (n_atoms > 0) {
-      const ckt_p kt = (ckt_p)KT64 + (int64_t)run * n_atoms * 12;
-      const int e0 = goff[g], e1 = goff[g + 1];
-      for (int e = e0; e < e1; ++e) {
-        const int key = gkey[e];
-        const double4 uu = reinterpret_cast<const double4*>(grp_u)[(int64_t)e * KG + lane];
-        const double us[4] = {uu.x, uu.y, uu.z, uu.w};
-        const ckt_p kp = kt + (int64_t)(key >> 2) * 12 + (key & 3) * 4;
+  const int nl = min(nlogical, *count * nchunks);
+  for (int lb = blockIdx.x; lb < nl; lb += gridDim.x) {
+    const int slot = lb / nchunks, ch = lb - slot * nchunks;
+    const int run = __builtin_amdgcn_readfirstlane(list[slot]);
+    if (status[run] != need) continue;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double2* v = V + (int64_t)(run % L) * N;
+    const double2* vdual = Vd + (int64_t)(run % L) * N;
+    typedef const CBS_CONST_AS int32_t* cint_p;
+    typedef const CBS_CONST_AS Pair<double>* ckt_p;
+    const cint_p goff = (cint_p)grp_off;
+    const cint_p gkey = (cint_p)grp_key;
+    const int64_t ngroups = (N + KG - 1) / KG;
+    const int64_t gpc = (ngroups + nchunks - 1) / nchunks;
+    const int64_t g0 = ch * gpc;
+    const int64_t g1 = (g0 + gpc < ngroups) ? g0 + gpc : ngroups;
+    double s[4] = {0, 0, 0, 0};
+    for (int64_t g = g0 + wv; g < g1; g += 4) {
+      const int64_t n = g * KG + lane;
+      Pair<double> k;
+      k.a = make_double2(0, 0);
+      k.b = k.a;
+      if (n_atoms > 0) {
+        const ckt_p kt = (ckt_p)KT64 + (int64_t)run * n_atoms * 12;
+        const int e0 = goff[g], e1 = goff[g + 1];
+        for (int e = e0; e < e1; ++e) {
+          const int key = gkey[e];
+          const double4 uu = reinterpret_cast<const double4*>(grp_u)[(int64_t)e * KG + lane];
+          const double us[4] = {uu.x, uu.y, uu.z, uu.w};
+          const ckt_p kp = kt + (int64_t)(key >> 2) * 12 + (key & 3) * 4;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const Pair<double> kk = kp[i];
-          k.a = cfma_r<double>(k.a, us[i], kk.a);
-          k.b = cfma_r<double>(k.b, us[i], kk.b);
+          for (int i = 0; i < 4; ++i) {
+            const Pair<double> kk = kp[i];
+            k.a = cfma_r<double>(k.a, us[i], kk.a);
+            k.b = cfma_r<double>(k.b, us[i], kk.b);
+          }
         }
       }
+      if (n < N) {
+        const int64_t gi = (int64_t)run * N + n;
+        const Pair<double> q = Q64[gi];
+        Pair<double> r64;
+        r64.a = csub<double>(v[n], cadd<double>(q.a, k.a));
+        r64.b = csub<double>(vdual[n], cadd<double>(q.b, k.b));
+        Pair<T> r;
+        r.a = ccast<T, double>(r64.a);
+        r.b = ccast<T, double>(r64.b);
+        R[gi] = r;
+        if (R64 != nullptr) R64[gi] = r64;
+        const cplx<T> rho = cmulc<T>(r.b, r.a);
+        s[0] += (double)rho.x;
+        s[1] += (double)rho.y;
+        s[2] += cabs2<double>(r64.a);
+        s[3] += cabs2<double>(r64.b);
+      }
     }
-    if (n < N) {
-      const int64_t gi = (int64_t)run * N + n;
-      const Pair<double> q = Q64[gi];
-      Pair<double> r64;
-      r64.a = csub<double>(v[n], cadd<double>(q.a, k.a));
-      r64.b = csub<double>(vdual[n], cadd<double>(q.b, k.b));
-      Pair<T> r;
-      r.a = ccast<T, double>(r64.a);
-      r.b = ccast<T, double>(r64.b);
-      R[gi] = r;
-      if (R64 != nullptr) R64[gi] = r64;
-      const cplx<T> rho = cmulc<T>(r.b, r.a);
-      s[0] += (double)rho.x;
-      s[1] += (double)rho.y;
-      s[2] += cabs2<double>(r64.a);
-      s[3] += cabs2<double>(r64.b);
-    }
+    for (int k = 0; k < 4; ++k) s[k] = wsum<double>(s[k]);
+    if (lane == 0)
+      for (int k = 0; k < 4; ++k) red[wv][k] = s[k];
+    __syncthreads();
+    if (tid < 4) part[((int64_t)run * nchunks + ch) * 4 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    __syncthreads();   // red is reused by the next work item
   }
-  for (int k = 0; k < 4; ++k) s[k] = wsum<double>(s[k]);
-  if (lane == 0)
-    for (int k = 0; k < 4; ++k) red[wv][k] = s[k];
-  __syncthreads();
-  if (tid < 4) part[((int64_t)run * nchunks + ch) * 4 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
 // Runs that went back to complex128 this iteration (conv == 1) restart from their
@@ -441,13 +446,30 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
   build_ru_list(sc, nruns);
 }
 
-__global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
+__global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t nchunks, double* part,
                                             double tol, int32_t max_iter, int32_t max_ru, double ru_factor) {
+  // the partial sums of each replaced run (listed by k_s2): the whole block adds them up and
+  // leaves the totals in the run's first chunk slot
+  __shared__ double red[4][4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nlist = sc.n_active[2];
+  for (int i = 0; i < nlist; ++i) {
+    const int run = sc.list[2 * (int64_t)nruns + i];
+    double t[4] = {0, 0, 0, 0};
+    for (int c = tid; c < nchunks; c += 256)
+      for (int k = 0; k < 4; ++k) t[k] += part[((int64_t)run * nchunks + c) * 4 + k];
+    for (int k = 0; k < 4; ++k) t[k] = wsum<double>(t[k]);
+    if (lane == 0)
+      for (int k = 0; k < 4; ++k) red[wv][k] = t[k];
+    __syncthreads();
+    if (tid < 4) part[(int64_t)run * nchunks * 4 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    __syncthreads();
+  }
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
     int st = sc.status[run];
     if (is_ru(st)) {
       double s[4];
-      sum_part(part, (int64_t)run * nchunks, nchunks, s);
+      for (int k = 0; k < 4; ++k) s[k] = part[(int64_t)run * nchunks * 4 + k];
       const double vn = sc.vn2[run];
       const double rr = sqrt(s[2] / vn), rrt = sqrt(s[3] / vn);
       sc.relres[2 * run] = rr;
@@ -551,7 +573,8 @@ int32_t bicg_alloc(BicgSolve& b, const char* tag) {
   const int na = s->proj.n_atoms;
   CBS_TRY(ws_get(ws, (t + ".signl").c_str(), R * std::max(na, 1), &b.signl));
   CBS_TRY(ws_get(ws, (t + ".upd").c_str(), R * b.nchunks * 4, &b.upd_part));
-  CBS_TRY(ws_get(ws, (t + ".ru").c_str(), R * b.nchunks * 4, &b.ru_part));
+  b.ru_chunks = (int32_t)(((s->N + KG - 1) / KG + 3) / 4);   // one group per wave
+  CBS_TRY(ws_get(ws, (t + ".ru").c_str(), R * b.ru_chunks * 4, &b.ru_part));
   CBS_TRY(ws_get(ws, (t + ".alpha").c_str(), R, &b.sc.alpha));
   CBS_TRY(ws_get(ws, (t + ".xcoef").c_str(), R, &b.sc.xcoef));
   CBS_TRY(ws_get(ws, (t + ".beta").c_str(), R, &b.sc.beta));
@@ -641,11 +664,13 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
   // residual replacement of the runs on the list built by k_s2 (and k_half_stop)
   const int32_t* rul = b.sc.list + 2 * (size_t)b.nruns;
   const int32_t* ruc = b.sc.n_active + 2;
+  const int nlr = b.nruns * b.ru_chunks;
+  const int gru = std::min(grid8(nlr), 2048);
   if (b.mixed)
-    hipLaunchKernelGGL(k_ru_pre<float>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, rul, ruc,
+    hipLaunchKernelGGL(k_ru_pre<float>, dim3(gru), dim3(256), 0, st, s->N, b.ru_chunks, nlr, rul, ruc,
                        (const int32_t*)b.sc.status, (int32_t)ST_RU_LO, (const double2*)b.sc.xcoef,
                        (const Pair<float>*)b.lo.Pb[parity & 1], b.lo.X, b.Y);
-  hipLaunchKernelGGL(k_ru_pre<double>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, rul, ruc,
+  hipLaunchKernelGGL(k_ru_pre<double>, dim3(gru), dim3(256), 0, st, s->N, b.ru_chunks, nlr, rul, ruc,
                      (const int32_t*)b.sc.status, (int32_t)ST_RU_HI, (const double2*)b.sc.xcoef,
                      (const Pair<double>*)b.hi.Pb[parity & 1], b.hi.X, b.Y);
   CBS_HIP(hipGetLastError());
@@ -657,21 +682,23 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
     r.coef = b.coef;
     r.list = rul;
     r.count = ruc;
+    r.zseg = 4;   // the list is short: four z segments per tile shorten each workgroup's march
     CBS_TRY(launch_stencil<double>(s, false, r, b.hi.tile_y, st));
     if (na > 0)
-      CBS_TRY(launch_bra<double>(s, b.nruns, b.Y, b.coef, nullptr, 0, b.hi.KT, nullptr, st, true, rul, ruc));
+      CBS_TRY(launch_bra<double>(s, b.nruns, b.Y, b.coef, nullptr, 0, b.hi.KT, nullptr, st, true, rul, ruc,
+                                 true));
   }
   if (b.mixed)
-    hipLaunchKernelGGL(k_ru_post<float>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, rul, ruc, b.L, na,
+    hipLaunchKernelGGL(k_ru_post<float>, dim3(gru), dim3(256), 0, st, s->N, b.ru_chunks, nlr, rul, ruc, b.L, na,
                        (const int32_t*)b.sc.status, (int32_t)ST_RU_LO, b.V, b.Vd ? b.Vd : b.V,
                        (const Pair<double>*)b.hi.Q, (const Pair<double>*)b.hi.KT, s->proj.grp_off, s->proj.grp_key,
                        (const double*)s->proj.grp_u64, b.lo.R, b.hi.R, b.ru_part);
-  hipLaunchKernelGGL(k_ru_post<double>, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, rul, ruc, b.L, na,
+  hipLaunchKernelGGL(k_ru_post<double>, dim3(gru), dim3(256), 0, st, s->N, b.ru_chunks, nlr, rul, ruc, b.L, na,
                      (const int32_t*)b.sc.status, (int32_t)ST_RU_HI, b.V, b.Vd ? b.Vd : b.V,
                      (const Pair<double>*)b.hi.Q, (const Pair<double>*)b.hi.KT, s->proj.grp_off, s->proj.grp_key,
                      (const double*)s->proj.grp_u64, b.hi.R, (Pair<double>*)nullptr, b.ru_part);
   CBS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_s3, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.ru_part, b.tol,
+  hipLaunchKernelGGL(k_s3, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.ru_chunks, b.ru_part, b.tol,
                      b.max_iter, b.max_ru, b.ru_factor);
   CBS_HIP(hipGetLastError());
   if (b.mixed) {

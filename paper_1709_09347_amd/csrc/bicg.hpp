@@ -63,6 +63,7 @@ struct BicgVecs {
 struct BicgSolve {
   cbs_system* sys = nullptr;
   int32_t nruns = 0, L = 1, n_q = 0, nchunks = 0;
+  int32_t ru_chunks = 0;   // work chunks per run of the residual replacement (ru_part)
   const double2* V = nullptr;       // [L][N]; run r uses right-hand side r % L
   const double2* Vd = nullptr;      // dual right-hand sides (same indexing), NULL: V
   const RunCoef* coef = nullptr;    // [nruns]

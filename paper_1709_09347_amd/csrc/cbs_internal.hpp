@@ -281,6 +281,7 @@ struct StencilLaunch {
   double2* sig_part;        // BiCG [nruns*ntiles]
   const int32_t* list;      // device [nruns] active runs (ascending) or NULL: all runs
   const int32_t* count;     // device: entries of list (with list)
+  int32_t zseg;             // apply only: z segments per tile (0 or 1: one), for short run lists
 };
 template <typename R>
 int32_t launch_stencil(const cbs_system* s, bool bicg, const StencilLaunch& a, int32_t tile_y,
@@ -295,7 +296,7 @@ template <typename R>
 int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunCoef* coef,
                    const int32_t* status, int32_t need_status, void* kt, double2* signl,
                    hipStream_t st, bool phased, const int32_t* list = nullptr,
-                   const int32_t* count = nullptr);
+                   const int32_t* count = nullptr, bool short_list = false);
 
 // Fused pointwise kernels.
 template <typename R>

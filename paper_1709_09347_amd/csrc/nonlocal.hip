@@ -137,8 +137,10 @@ __device__ __forceinline__ mf4<float>::T mfma16x16x4(float a, float b, mf4<float
 }
 
 // R: storage precision (vectors, tables, K); C: arithmetic precision (MFMA, sums).
-template <typename R, typename C>
-__global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
+// NW waves per workgroup share each (atom, 16 runs): 4 for full batches; 16 when the run
+// list is short (residual replacement), so the few workgroups walk their balls 4x faster.
+template <typename R, typename C, int NW>
+__global__ void __launch_bounds__(64 * NW) k_bra_mfma(BraArgs<R> a) {
   __shared__ cplx<C> cs[16][2][4];
   __shared__ int srun[16];
   // slots: the runs themselves, or the entries of the active-run list
@@ -164,12 +166,12 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
   }
   if (!__syncthreads_or(any)) return;
   // Every wave covers all 16 runs (four groups g of 4 runs: four independent MFMA chains
-  // that share each table load) over every 4th step of 4 ball entries; the four waves'
+  // that share each table load) over every NW-th step of 4 ball entries; the waves'
   // partial products are summed through LDS.  The ball's entries come in three segments
   // by cell shift w = -1, 0, +1; each segment is contracted without its Bloch phase, which
   // multiplies the segment's complex sums afterwards (c += z^w c_w), so the inner loop
   // holds no phase factors.
-  __shared__ C red[4][4][16][4];
+  __shared__ C red[NW][4][16][4];
   __shared__ cplx<C> cw[16][2][4];
   const int row = lane & 15, kslot = lane >> 4, col = lane & 15;
   const int half = (row >> 1) & 1, reim = row & 1;
@@ -200,14 +202,15 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
       // segment carry a zero projector value and rows of empty run slots are discarded,
       // so the gathered values need no masking.
       const int e_first = sa + 4 * wv + kslot;
+      constexpr int STEP = 4 * NW;   // entries per step of the whole workgroup
       const int el = min(e_first, sb - 1);
       int idx0 = a.idx[el];
       C bv0 = (e_first < sb && col < 4) ? (C)a.u[4 * (int64_t)el + (col & 3)] : (C)0;
-      for (int e = e_first; e - kslot < sb; e += 16) {
+      for (int e = e_first; e - kslot < sb; e += STEP) {
         C vv[4];
 #pragma unroll
         for (int g = 0; g < 4; ++g) vv[g] = (C)vrow[g][4 * (int64_t)idx0];
-        const int e1 = e + 16;
+        const int e1 = e + STEP;
         const int e1l = min(e1, sb - 1);
         const int idx1 = a.idx[e1l];
         const C u1 = (C)a.u[4 * (int64_t)e1l + (col & 3)];
@@ -218,7 +221,7 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
         bv0 = bv1;
       }
     } else {
-      for (int e0 = sa + 4 * wv; e0 < sb; e0 += 16) {
+      for (int e0 = sa + 4 * wv; e0 < sb; e0 += 4 * NW) {
         const int e = e0 + kslot;
         const bool ok = e < sb;
         const int elc = min(e, sb - 1);
@@ -242,13 +245,15 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
     }
     __syncthreads();
     {
-      // thread t < 256: group g = t/64 reduces lane t%64 over the four waves
+      // thread t < 256: group g = t/64 reduces lane t%64 over the NW waves
       const int g = tid >> 6, l2 = tid & 63;
-      if ((l2 & 15) < 4) {
+      if (tid < 256 && (l2 & 15) < 4) {
         const int q = (l2 >> 4) * 4 + (l2 & 15);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const C sum = red[0][g][q][v] + red[1][g][q][v] + red[2][g][q][v] + red[3][g][q][v];
+          C sum = 0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) sum += red[w][g][q][v];
           const int r = mfma16_row<C>(l2, v);   // output row held by lane l2
           C* dst = reinterpret_cast<C*>(&cw[4 * g + (r >> 2)][(r >> 1) & 1][l2 & 15]);
           dst[r & 1] = sum;
@@ -270,7 +275,7 @@ __global__ void __launch_bounds__(256) k_bra_mfma(BraArgs<R> a) {
     __syncthreads();
   }
   const RunCoef* cfp = a.coef;
-  for (int t = tid; t < 16 * 24; t += 256) {
+  for (int t = tid; t < 16 * 24; t += 64 * NW) {
     const int r2 = t / 24, rem = t - r2 * 24;
     const int h2 = rem & 1, i = (rem >> 1) & 3, sw = rem >> 3;
     const int rr = srun[r2];
@@ -304,7 +309,8 @@ static bool bra_plain() {
 template <typename R>
 int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunCoef* coef,
                    const int32_t* status, int32_t need_status, void* kt, double2* signl,
-                   hipStream_t st, bool phased, const int32_t* list, const int32_t* count) {
+                   hipStream_t st, bool phased, const int32_t* list, const int32_t* count,
+                   bool short_list) {
   const Projector& pr = s->proj;
   if (pr.n_atoms == 0 || nruns <= 0) return CBS_OK;
   BraArgs<R> a;
@@ -333,10 +339,15 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
   if (phased && !bra_plain()) {
     a.nlogical = ((nruns + 15) / 16) * pr.n_atoms;
     const int grid = (a.nlogical + 7) / 8 * 8;
-    if (std::is_same<R, float>::value && lo_arith_fp32())
-      hipLaunchKernelGGL((k_bra_mfma<R, float>), dim3(grid), dim3(256), 0, st, a);
+    const bool f32 = std::is_same<R, float>::value && lo_arith_fp32();
+    if (short_list && f32)
+      hipLaunchKernelGGL((k_bra_mfma<R, float, 16>), dim3(grid), dim3(1024), 0, st, a);
+    else if (short_list)
+      hipLaunchKernelGGL((k_bra_mfma<R, double, 16>), dim3(grid), dim3(1024), 0, st, a);
+    else if (f32)
+      hipLaunchKernelGGL((k_bra_mfma<R, float, 4>), dim3(grid), dim3(256), 0, st, a);
     else
-      hipLaunchKernelGGL((k_bra_mfma<R, double>), dim3(grid), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_bra_mfma<R, double, 4>), dim3(grid), dim3(256), 0, st, a);
   } else {
     const int grid = (a.nlogical + 7) / 8 * 8;
     hipLaunchKernelGGL(k_bra<R>, dim3(grid), dim3(256), 0, st, a);
@@ -672,7 +683,7 @@ int32_t launch_from_pairs(int64_t N, int32_t nvec, const void* pairs, void* y, h
 #define INST(R)                                                                                   \
   template int32_t launch_bra<R>(const cbs_system*, int32_t, const void*, const RunCoef*,         \
                                  const int32_t*, int32_t, void*, double2*, hipStream_t, bool,     \
-                                 const int32_t*, const int32_t*);                                 \
+                                 const int32_t*, const int32_t*, bool);                           \
   template int32_t launch_update<R>(const cbs_system*, int32_t, void*, const void*, const void*,  \
                                     const double2*, const int32_t*, int32_t, double*, int32_t,    \
                                     hipStream_t, const int32_t*, const int32_t*);                 \

@@ -25,6 +25,7 @@ namespace cbs {
 template <typename R>
 struct StArgs {
   int32_t nx, ny, nz, ty, ntiles, nlogical, nbuf;
+  int32_t nzseg;          // z segments per tile (1 for the BiCG stencil)
   int64_t N;
   double kin;   // -1/(2 h^2)
   double c[5];  // c_0..c_p
@@ -61,11 +62,18 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
   __shared__ double2 red[8];
   Pair<R>* lds = reinterpret_cast<Pair<R>*>(smem_raw);
 
-  const int nl = (a.list != nullptr) ? min(a.nlogical, *a.count * a.ntiles) : a.nlogical;
+  const int per_run = a.ntiles * a.nzseg;
+  const int nl = (a.list != nullptr) ? min(a.nlogical, *a.count * per_run) : a.nlogical;
   const int lb = remap_active(blockIdx.x, nl);
   if (lb < 0) return;
-  const int slot = lb / a.ntiles;
-  const int tile = lb - slot * a.ntiles;
+  const int slot = lb / per_run;
+  const int rem = lb - slot * per_run;
+  const int tile = rem / a.nzseg;
+  // z segment [z0, z1) of the outputs; the march covers p halo planes on either side
+  const int zlen = (a.nz + a.nzseg - 1) / a.nzseg;
+  const int z0 = (rem - tile * a.nzseg) * zlen;
+  const int z1 = min(z0 + zlen, a.nz);
+  if (z0 >= z1) return;
   const int run = (a.list != nullptr) ? a.list[slot] : slot;
   if (a.status != nullptr && a.status[run] != a.need_status) return;
 
@@ -175,9 +183,10 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
       }
     }
   };
-  if (pipe) issue(0);
+  const int m_end = z1 + P, real_end = min(nz, m_end);
+  if (pipe && max(z0 - P, 0) < real_end) issue(max(z0 - P, 0));
 
-  for (int m = -P; m < nz + P; ++m) {
+  for (int m = z0 - P; m < m_end; ++m) {
     const bool real = (m >= 0) && (m < nz);
     Pair<C> s;
     s.a = mkc<C>(0, 0);
@@ -188,7 +197,7 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
       if (a.nbuf == 1 && m > 0) __syncthreads();   // single buffer: previous plane fully read
       if (pipe) {
         commit(m, buf);
-        if (m + 1 < nz) issue(m + 1);
+        if (m + 1 < real_end) issue(m + 1);
       }
       for (int e = tid; e < region && !pipe; e += nthr) {
         const int r = e / nx;
@@ -283,7 +292,7 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
         acc[P].b = cadd<C>(acc[P].b, inb.b);
       }
       const int o = m - P;
-      if (o >= 0) {
+      if (o >= z0) {
         a.q[base + tx + (int64_t)nx * y + plane * o] = pcast<R, C>(acc[0]);
         if (BICG) {
           const cplx<C> t = cmulc<C>(pdq[0], acc[0].a);
@@ -367,7 +376,8 @@ int32_t launch_stencil(const cbs_system* s, bool bicg, const StencilLaunch& l, i
   a.ty = tile_y;
   a.ntiles = stencil_tiles(s, tile_y);
   a.nbuf = ((size_t)2 * (tile_y + 2 * s->p) * s->nx * sizeof(Pair<R>) <= 64 * 1024) ? 2 : 1;
-  a.nlogical = l.nruns * a.ntiles;
+  a.nzseg = bicg ? 1 : std::max(1, std::min<int32_t>(l.zseg, s->nz));
+  a.nlogical = l.nruns * a.ntiles * a.nzseg;
   a.N = s->N;
   a.kin = -0.5 / (s->h * s->h);
   for (int i = 0; i < 5; ++i) a.c[i] = s->fd[i];
