@@ -377,36 +377,43 @@ __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t 
   build_lists(sc, nruns);
 }
 
+// One wavefront per run: the lanes add the stencil's per-tile and the bra's per-atom
+// partials of sigma = pt^H q, lane 0 sets alpha.
 __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t n_atoms, const double2* sig_lo,
                                             int32_t nt_lo, const double2* sig_hi, int32_t nt_hi,
                                             const double2* signl) {
-  for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
-    const int st = sc.status[run];
-    if (!is_active(st)) continue;
-    const double2* sp = (st == ST_ACT_LO) ? sig_lo : sig_hi;
-    const int nt = (st == ST_ACT_LO) ? nt_lo : nt_hi;
-    double2 sg = make_double2(0, 0);
-    for (int t = 0; t < nt; ++t) {
-      const double2 v = sp[(int64_t)run * nt + t];
-      sg.x += v.x;
-      sg.y += v.y;
-    }
-    for (int a = 0; a < n_atoms; ++a) {
+  const int lane = threadIdx.x & 63;
+  const int run = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (run >= nruns) return;
+  const int st = sc.status[run];
+  if (!is_active(st)) return;
+  const double2* sp = (st == ST_ACT_LO) ? sig_lo : sig_hi;
+  const int nt = (st == ST_ACT_LO) ? nt_lo : nt_hi;
+  double2 sg = make_double2(0, 0);
+  for (int t = lane; t < nt; t += 64) {
+    const double2 v = sp[(int64_t)run * nt + t];
+    sg.x += v.x;
+    sg.y += v.y;
+  }
+  if (signl != nullptr)
+    for (int a = lane; a < n_atoms; a += 64) {
       const double2 v = signl[(int64_t)run * n_atoms + a];
       sg.x += v.x;
       sg.y += v.y;
     }
-    if (!(sg.x != 0.0 || sg.y != 0.0) || !finite2(sg)) {
-      sc.brk[run] = 1;
-      sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
-      sc.alpha[run] = make_double2(0, 0);
-      sc.xcoef[run] = make_double2(0, 0);
-      continue;
-    }
-    const double2 al = cdiv<double>(sc.rho[run], sg);
-    sc.alpha[run] = al;
-    sc.xcoef[run] = al;
+  sg.x = wsum<double>(sg.x);
+  sg.y = wsum<double>(sg.y);
+  if (lane != 0) return;
+  if (!(sg.x != 0.0 || sg.y != 0.0) || !finite2(sg)) {
+    sc.brk[run] = 1;
+    sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
+    sc.alpha[run] = make_double2(0, 0);
+    sc.xcoef[run] = make_double2(0, 0);
+    return;
   }
+  const double2 al = cdiv<double>(sc.rho[run], sg);
+  sc.alpha[run] = al;
+  sc.xcoef[run] = al;
 }
 
 __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
@@ -646,8 +653,8 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
   const int nl = b.nruns * b.nchunks;
   if (b.mixed) CBS_TRY(enqueue_stencil_bra<float>(b, b.lo, ST_ACT_LO, parity, st));
   CBS_TRY(enqueue_stencil_bra<double>(b, b.hi, ST_ACT_HI, parity, st));
-  hipLaunchKernelGGL(k_s1, dim3(1), dim3(256), 0, st, b.sc, b.nruns, na, (const double2*)b.lo.sig, b.lo.ntiles,
-                     (const double2*)b.hi.sig, b.hi.ntiles, (const double2*)b.signl);
+  hipLaunchKernelGGL(k_s1, dim3((b.nruns + 3) / 4), dim3(256), 0, st, b.sc, b.nruns, na, (const double2*)b.lo.sig,
+                     b.lo.ntiles, (const double2*)b.hi.sig, b.hi.ntiles, (const double2*)b.signl);
   CBS_HIP(hipGetLastError());
   if (b.mixed)
     CBS_TRY(launch_update<float>(s, b.nruns, b.lo.R, b.lo.Q, b.lo.KT, b.sc.alpha, b.sc.status, ST_ACT_LO,
