@@ -347,9 +347,13 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
   CBS_HIP(hipMemcpyAsync(dinv, inv.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
   CBS_TRY(small_gemm(m, m, n, Up, n, true, TW, n, Bred, m, dinv, nullptr, st));
   dump("Bred", Bred, (size_t)m * m * sizeof(c64), st);
-  CBS_TRY(eig(s, m, Bred, m, tau, phi, m, info, st));
-  dump("tau", tau, (size_t)m * sizeof(c64), st);
-  dump("phi", phi, (size_t)m * m * sizeof(c64), st);
+  if (prm->extraction == CBS_HANKEL) {
+    // the reduced Hankel eigenpairs are the result only for the Hankel extraction; the
+    // Rayleigh-Ritz extraction uses the SVD basis alone
+    CBS_TRY(eig(s, m, Bred, m, tau, phi, m, info, st));
+    dump("tau", tau, (size_t)m * sizeof(c64), st);
+    dump("phi", phi, (size_t)m * m * sizeof(c64), st);
+  }
 
   std::vector<c64> cand;
   c64* basis = nullptr;   // N x ncand candidate vectors (not normalised)
