@@ -12,10 +12,10 @@
 //   S1  alpha = rho / sigma
 //   B   r -= alpha (q + ket), rt -= conj(alpha) (qt + ket); rho, ||r||^2, ||rt||^2
 //   S2  beta = rho_new / rho; tests on the recursive residuals
-//   RU  residual replacement for the runs S2 marked: the iterate is accumulated into
-//       the complex128 solution y, the true residual v - P y is recomputed in complex128
-//       and replaces r; the search direction is kept, so the Krylov space is not
-//       restarted.
+//   RU  residual replacement for the runs S2 marked (a compact list, launches shaped for
+//       few runs): the iterate is accumulated into the complex128 solution y, the true
+//       residual v - P y is recomputed in complex128 and replaces r; the search direction
+//       is kept, so the Krylov space is not restarted.
 //   S3  decisions on the true residual (done / continue / change phase), active counts.
 // Precision (mixed mode) follows the relaxation of inexact Krylov methods: the error
 // allowed in an operator application grows as the residual shrinks.  Every run starts

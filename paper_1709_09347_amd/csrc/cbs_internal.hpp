@@ -100,9 +100,6 @@ __device__ __forceinline__ int mfma16_row(int lane, int v) {
   return sizeof(R) == 8 ? 4 * v + (lane >> 4) : 4 * (lane >> 4) + v;
 }
 
-// Remap a block id so that consecutive logical blocks run on one XCD (the
-// dispatcher hands blocks to the 8 XCDs round-robin); gridDim must be a
-// multiple of 8.
 // Address space for data read at wave-uniform addresses (the compiler then uses scalar
 // loads); the host pass of the same source has no address spaces.
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -119,6 +116,9 @@ inline bool lo_arith_fp32() {
   return !(e && e[0] == '6' && e[1] == '4');
 }
 
+// Remap a block id so that consecutive logical blocks run on one XCD (the
+// dispatcher hands blocks to the 8 XCDs round-robin); gridDim must be a
+// multiple of 8.
 __device__ __forceinline__ int xcd_remap(int bid, int nb) { return (bid & 7) * (nb >> 3) + (bid >> 3); }
 
 // Logical block of a launch whose first nl logical blocks carry work (nl may be below the

@@ -6,11 +6,13 @@
 //     sum_{a,i} h_ai sum_{w,w'} coef(w'-w) u_{a,i,w} u_{a,i,w'}^T,
 // coef(0) = c0, coef(1) = cp, coef(-1) = cm (P(z): 1, z, 1/z).  It is applied in two
 // passes per run:
-//   bra:  G[a][w'][i] = u_{a,i,w'}^T v            (one workgroup per atom and run)
+//   bra:  G[a][w'][i] = u_{a,i,w'}^T v            (one workgroup per atom and 16 runs,
+//                                                  MFMA; a plain kernel per atom and run)
 //         K[a][w][i]  = h_ai sum_w' coef(w'-w) G[a][w'][i]
 //   ket:  y(n) += sum_{entries e at point n} sum_i u_{e,i} K[a_e][w_e][i]
-// The ket runs inside the pointwise kernels (BiCG residual update, apply), reading a
-// point-major copy of the tables so no two threads ever add into the same point.
+// The ket runs inside the pointwise kernels (BiCG residual update, apply), reading
+// point-ordered tables (per point, or per 64-point group and key in the update) so no two
+// threads ever add into the same point.
 // For BiCG the bra also yields the nonlocal part of sigma = pt^H P p:
 //   sum_{a,i} h_ai conj(ct_ai) c_ai,  c = G_0 + z G_1 + z^-1 G_-1 (dual: 1/conj z).
 #include <algorithm>
