@@ -220,36 +220,31 @@ __global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int
   }
 }
 
-// Runs that went back to complex128 this iteration (conv == 1) restart from their
-// replaced residual: the old complex128 direction is cleared (beta is 0, and a stale
-// value must not turn 0 * p into NaN).
-__global__ void __launch_bounds__(256) k_widen(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* conv,
-                                               Pair<double>* Phi) {
+// Phase changes decided this iteration (conv flags, cleared by the next k_s2):
+//   conv == 1: the run went back to complex128 and restarts from its replaced residual;
+//              the old complex128 direction is cleared (beta is 0, and a stale value must
+//              not turn 0 * p into NaN);
+//   conv == 2: the run entered the complex64 phase: r and the latest search direction are
+//              rounded to complex64, the complex128 iterate is accumulated into y and both
+//              iterates restart from zero.
+__global__ void __launch_bounds__(256) k_phase(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* conv,
+                                               const Pair<double>* Rhi, Pair<double>* Phi, Pair<double>* Xhi,
+                                               Pair<float>* Rlo, Pair<float>* Plo, Pair<float>* Xlo,
+                                               Pair<double>* Y) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   if (lb >= nlogical) return;
   const int run = lb / nchunks, ch = lb - run * nchunks;
-  if (conv[run] != 1) return;   // 2 marks a narrowing, handled by k_narrow
+  const int cv = conv[run];
+  if (cv != 1 && cv != 2) return;
   const int64_t chunk = (N + nchunks - 1) / nchunks;
   const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
-  Pair<double> z;
-  z.a = make_double2(0, 0);
-  z.b = z.a;
-  for (int64_t n = lo + threadIdx.x; n < hi; n += 256) Phi[(int64_t)run * N + n] = z;
-}
-
-// Narrow the runs that entered the complex64 phase this iteration (conv == 2): r and
-// the latest search direction are rounded to complex64, the complex128 iterate is
-// accumulated into y and both iterates restart from zero.
-__global__ void __launch_bounds__(256) k_narrow(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* conv,
-                                                const Pair<double>* Rhi, const Pair<double>* Phi, Pair<double>* Xhi,
-                                                Pair<float>* Rlo, Pair<float>* Plo, Pair<float>* Xlo,
-                                                Pair<double>* Y) {
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  if (lb >= nlogical) return;
-  const int run = lb / nchunks, ch = lb - run * nchunks;
-  if (conv[run] != 2) return;
-  const int64_t chunk = (N + nchunks - 1) / nchunks;
-  const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
+  Pair<double> zd;
+  zd.a = make_double2(0, 0);
+  zd.b = zd.a;
+  if (cv == 1) {
+    for (int64_t n = lo + threadIdx.x; n < hi; n += 256) Phi[(int64_t)run * N + n] = zd;
+    return;
+  }
   for (int64_t n = lo + threadIdx.x; n < hi; n += 256) {
     const int64_t g = (int64_t)run * N + n;
     const Pair<double> r = Rhi[g], p = Phi[g], x = Xhi[g];
@@ -267,9 +262,6 @@ __global__ void __launch_bounds__(256) k_narrow(int64_t N, int32_t nchunks, int3
     y.a = cadd<double>(y.a, x.a);
     y.b = cadd<double>(y.b, x.b);
     Y[g] = y;
-    Pair<double> zd;
-    zd.a = make_double2(0, 0);
-    zd.b = zd.a;
     Xhi[g] = zd;
   }
 }
@@ -419,6 +411,9 @@ __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t 
 __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
                                             double tol, int32_t max_iter, double narrow_tol, double ru_factor,
                                             int32_t lo_window) {
+  // the previous iteration's phase changes are done (k_phase ran after k_s3)
+  for (int run = threadIdx.x; run < nruns; run += blockDim.x) sc.conv[run] = 0;
+  __syncthreads();
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
     const int st = sc.status[run];
     if (!is_active(st)) continue;
@@ -519,10 +514,6 @@ __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t 
   }
   __syncthreads();
   build_lists(sc, nruns);
-}
-
-__global__ void k_clear_conv(BicgScal sc, int32_t nruns) {
-  for (int run = threadIdx.x; run < nruns; run += blockDim.x) sc.conv[run] = 0;
 }
 
 // Half-of-the-nodes rule (paper Sec. 3.3): within every group of n_q*L runs, once more
@@ -709,12 +700,9 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
                      b.max_iter, b.max_ru, b.ru_factor);
   CBS_HIP(hipGetLastError());
   if (b.mixed) {
-    hipLaunchKernelGGL(k_widen, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, (const int32_t*)b.sc.conv,
-                       b.hi.Pb[parity & 1]);
-    hipLaunchKernelGGL(k_narrow, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, (const int32_t*)b.sc.conv,
-                       (const Pair<double>*)b.hi.R, (const Pair<double>*)b.hi.Pb[parity & 1], b.hi.X, b.lo.R,
-                       b.lo.Pb[parity & 1], b.lo.X, b.Y);
-    hipLaunchKernelGGL(k_clear_conv, dim3(1), dim3(256), 0, st, b.sc, b.nruns);
+    hipLaunchKernelGGL(k_phase, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, (const int32_t*)b.sc.conv,
+                       (const Pair<double>*)b.hi.R, b.hi.Pb[parity & 1], b.hi.X, b.lo.R, b.lo.Pb[parity & 1],
+                       b.lo.X, b.Y);
     CBS_HIP(hipGetLastError());
   }
   return CBS_OK;

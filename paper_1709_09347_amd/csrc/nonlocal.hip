@@ -364,13 +364,10 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
 template <typename R>
 struct UpdArgs {
   int32_t nchunks, nlogical, n_atoms, need_status, nruns;
-  int64_t N, chunk;
+  int64_t N;
   Pair<R>* r;
   const Pair<R>* q;
   const Pair<R>* kt;
-  const int32_t* pt_off;
-  const int32_t* pt_key;
-  const R* pt_u;
   const double2* alpha;
   const int32_t* status;
   double* part;   // [run][chunk][4]
@@ -578,13 +575,9 @@ int32_t launch_update(const cbs_system* s, int32_t nruns, void* r, const void* q
   a.nlogical = ((nruns + UR - 1) / UR) * nchunks;
   a.n_atoms = s->proj.n_atoms;
   a.N = s->N;
-  a.chunk = (s->N + nchunks - 1) / nchunks;
   a.r = (Pair<R>*)r;
   a.q = (const Pair<R>*)q;
   a.kt = (s->proj.n_atoms > 0) ? (const Pair<R>*)kt : nullptr;
-  a.pt_off = s->proj.pt_off;
-  a.pt_key = s->proj.pt_key;
-  a.pt_u = std::is_same<R, double>::value ? (const R*)s->proj.pt_u64 : (const R*)s->proj.pt_u32;
   a.alpha = alpha;
   a.status = status;
   a.part = part;
