@@ -90,8 +90,8 @@ def main():
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the path shards by quadrature node and "
-              "right-hand side; multi-GPU runs are not part of it)", file=sys.stderr)
+        print("bench.py: one GPU only (the path would shard by quadrature node and right-hand side; "
+              "runs on several GPUs are not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
