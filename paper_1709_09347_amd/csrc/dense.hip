@@ -378,7 +378,8 @@ __global__ void __launch_bounds__(SWG) k_eig(int32_t n, c64* H, int32_t ldh, c64
                                               c64* Z, c64* Y, int32_t* info) {
   __shared__ double sh[SWG / 64];
   __shared__ c64 sv[512];
-  __shared__ c64 sg[3];
+  __shared__ c64 sg[1];
+  __shared__ c64 sxy[2];   // (x, y) of the next Givens rotation of the sweep
   __shared__ int s_lo, s_hi, s_iter, s_done;
   const int tid = threadIdx.x;
   for (int t = tid; t < n * n; t += SWG) {
@@ -479,6 +480,8 @@ __global__ void __launch_bounds__(SWG) k_eig(int32_t n, c64* H, int32_t ldh, c64
         }
         sg[0] = mu;
         s_lo = l;
+        sxy[0] = zsub(H[l + (int64_t)l * ldh], mu);
+        sxy[1] = H[l + 1 + (int64_t)l * ldh];
         break;
       }
       s_hi = hi;
@@ -493,37 +496,26 @@ __global__ void __launch_bounds__(SWG) k_eig(int32_t n, c64* H, int32_t ldh, c64
     const int lo = s_lo, hi = s_hi;
     const c64 mu = sg[0];
     if (tid == 0) s_iter = s_iter + 1;
-    // implicit single-shift sweep: Givens rotations chase the bulge from lo to hi
+    // implicit single-shift sweep: Givens rotations chase the bulge from lo to hi.  The
+    // pair (x, y) that defines rotation k comes from the column update of rotation k-1
+    // (rows k and k+1 of column k-1, through LDS), so every thread forms (c, s) itself.
     for (int k = lo; k < hi; ++k) {
-      if (tid == 0) {
-        c64 x, y;
-        if (k == lo) {
-          x = zsub(H[lo + (int64_t)lo * ldh], mu);
-          y = H[lo + 1 + (int64_t)lo * ldh];
-        } else {
-          x = H[k + (int64_t)(k - 1) * ldh];
-          y = H[k + 1 + (int64_t)(k - 1) * ldh];
-        }
-        const double nx = zabs(x), ny = zabs(y);
-        const double r = hypot(nx, ny);
-        c64 cs, sn;   // G = [[c, s], [-conj(s), c]] with c real: G [x; y] = [r'; 0]
-        if (r == 0.0) {
-          cs = make_double2(1, 0);
-          sn = make_double2(0, 0);
-        } else if (nx == 0.0) {
-          cs = make_double2(0, 0);
-          sn = zscale(zconj(y), 1.0 / ny);
-        } else {
-          cs = make_double2(nx / r, 0.0);
-          const c64 ux = make_double2(x.x / nx, x.y / nx);   // phase of x
-          sn = zscale(zmul(ux, zconj(y)), 1.0 / r);
-        }
-        sg[1] = cs;
-        sg[2] = sn;
+      const c64 x = sxy[0], y = sxy[1];
+      const double nx = zabs(x), ny = zabs(y);
+      const double r = hypot(nx, ny);
+      double c;   // G = [[c, s], [-conj(s), c]] with c real: G [x; y] = [r'; 0]
+      c64 s;
+      if (r == 0.0) {
+        c = 1.0;
+        s = make_double2(0, 0);
+      } else if (nx == 0.0) {
+        c = 0.0;
+        s = zscale(zconj(y), 1.0 / ny);
+      } else {
+        c = nx / r;
+        const c64 ux = make_double2(x.x / nx, x.y / nx);   // phase of x
+        s = zscale(zmul(ux, zconj(y)), 1.0 / r);
       }
-      __syncthreads();
-      const double c = sg[1].x;
-      const c64 s = sg[2];
       // rows k, k+1: [hk; hk1] <- [c hk + s hk1; -conj(s) hk + c hk1], columns max(k-1,0)..n-1
       const int j0 = (k > lo) ? k - 1 : lo;
       for (int j = j0 + tid; j < n; j += SWG) {
@@ -536,20 +528,23 @@ __global__ void __launch_bounds__(SWG) k_eig(int32_t n, c64* H, int32_t ldh, c64
       const int rmax = std::min(k + 2, hi);
       for (int i = tid; i <= rmax + n; i += SWG) {
         c64* M;
-        int r, ld;
+        int r2, ld;
         if (i <= rmax) {
           M = H;
-          r = i;
+          r2 = i;
           ld = ldh;
         } else {
           M = Z;
-          r = i - rmax - 1;
+          r2 = i - rmax - 1;
           ld = n;
-          if (r >= n) continue;
+          if (r2 >= n) continue;
         }
-        const c64 mk = M[r + (int64_t)k * ld], mk1 = M[r + (int64_t)(k + 1) * ld];
-        M[r + (int64_t)k * ld] = zadd(zscale(mk, c), zmul(zconj(s), mk1));
-        M[r + (int64_t)(k + 1) * ld] = zsub(zscale(mk1, c), zmul(s, mk));
+        const c64 mk = M[r2 + (int64_t)k * ld], mk1 = M[r2 + (int64_t)(k + 1) * ld];
+        const c64 nk = zadd(zscale(mk, c), zmul(zconj(s), mk1));
+        M[r2 + (int64_t)k * ld] = nk;
+        M[r2 + (int64_t)(k + 1) * ld] = zsub(zscale(mk1, c), zmul(s, mk));
+        if (i <= rmax && r2 == k + 1) sxy[0] = nk;   // x of rotation k+1
+        if (i <= rmax && r2 == k + 2) sxy[1] = nk;   // y of rotation k+1 (the bulge)
       }
       __syncthreads();
     }
