@@ -272,6 +272,7 @@ __global__ void __launch_bounds__(JWG) k_jacobi_svd(int32_t n, c64* A, int32_t l
         double al = 0, be = 0;
         c64 ga = make_double2(0, 0);
         if (q < n) {
+#pragma unroll 4
           for (int i = sub; i < n; i += gsize) {
             const c64 ap = A[i + (int64_t)p * lda], aq = A[i + (int64_t)q * lda];
             al += cabs2<double>(ap);
@@ -294,13 +295,28 @@ __global__ void __launch_bounds__(JWG) k_jacobi_svd(int32_t n, c64* A, int32_t l
         const double t = ((zeta >= 0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
         const c64 e = make_double2(ga.x / g, -ga.y / g);   // e^{-i phi}
-        for (int i = sub; i < n; i += gsize) {
-          const c64 ap = A[i + (int64_t)p * lda], aq = zmul(e, A[i + (int64_t)q * lda]);
-          A[i + (int64_t)p * lda] = zsub(zscale(ap, c), zscale(aq, sn));
-          A[i + (int64_t)q * lda] = zadd(zscale(ap, sn), zscale(aq, c));
-          const c64 vp = V[i + (int64_t)p * ldv], vq = zmul(e, V[i + (int64_t)q * ldv]);
-          V[i + (int64_t)p * ldv] = zsub(zscale(vp, c), zscale(vq, sn));
-          V[i + (int64_t)q * ldv] = zadd(zscale(vp, sn), zscale(vq, c));
+        // two rows at a time: all their loads are issued before the first store (the
+        // compiler cannot tell that the stores do not alias the next rows' loads)
+        for (int i0 = sub; i0 < n; i0 += 2 * gsize) {
+          c64 ap[2], aq[2], vp[2], vq[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int i = min(i0 + u * gsize, n - 1);
+            ap[u] = A[i + (int64_t)p * lda];
+            aq[u] = A[i + (int64_t)q * lda];
+            vp[u] = V[i + (int64_t)p * ldv];
+            vq[u] = V[i + (int64_t)q * ldv];
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int i = i0 + u * gsize;
+            if (i >= n) break;
+            const c64 aqe = zmul(e, aq[u]), vqe = zmul(e, vq[u]);
+            A[i + (int64_t)p * lda] = zsub(zscale(ap[u], c), zscale(aqe, sn));
+            A[i + (int64_t)q * lda] = zadd(zscale(ap[u], sn), zscale(aqe, c));
+            V[i + (int64_t)p * ldv] = zsub(zscale(vp[u], c), zscale(vqe, sn));
+            V[i + (int64_t)q * ldv] = zadd(zscale(vp[u], sn), zscale(vqe, c));
+          }
         }
       }
       __syncthreads();
