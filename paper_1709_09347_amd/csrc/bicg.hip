@@ -408,49 +408,56 @@ __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t 
   sc.xcoef[run] = al;
 }
 
+// One wavefront per run: the lanes add the update's per-chunk partials, lane 0 takes the
+// decisions.  The list of runs marked for replacement is built afterwards (k_ru_list).
 __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
                                             double tol, int32_t max_iter, double narrow_tol, double ru_factor,
                                             int32_t lo_window) {
-  // the previous iteration's phase changes are done (k_phase ran after k_s3)
-  for (int run = threadIdx.x; run < nruns; run += blockDim.x) sc.conv[run] = 0;
-  __syncthreads();
-  for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
-    const int st = sc.status[run];
-    if (!is_active(st)) continue;
-    double s[4];
-    sum_part(part, (int64_t)run * nchunks, nchunks, s);
-    const int it = sc.iters[run] + 1;
-    sc.iters[run] = it;
-    const double vn = sc.vn2[run];
-    const double rr = sqrt(s[2] / vn), rrt = sqrt(s[3] / vn);
-    sc.relres[2 * run] = rr;
-    sc.relres[2 * run + 1] = rrt;
-    const double2 rn = make_double2(s[0], s[1]);
-    const double2 ro = sc.rho[run];
-    const bool conv = (rr < tol) && (rrt < tol);
-    const bool bad = !(rn.x != 0.0 || rn.y != 0.0) || !finite2(rn) || !isfinite(rr) || !isfinite(rrt);
-    if (bad && !conv) sc.brk[run] = 1;
-    sc.beta[run] = bad ? make_double2(0, 0) : cdiv<double>(rn, ro);
-    sc.rho_prev[run] = ro;
-    sc.rho[run] = rn;
-    const bool stalled = (st == ST_ACT_LO) && (it - sc.ru_it[run] >= lo_window);
-    if (conv || bad || it >= max_iter || fmax(rr, rrt) < sc.ru_thr[run] || stalled) {
-      sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
-    } else if (st == ST_ACT_HI && narrow_tol > 0.0 && sc.ru_thr[run] >= 0.0 && fmax(rr, rrt) < narrow_tol) {
-      // the residual is small enough for complex64 vectors and operator applications
-      sc.status[run] = ST_ACT_LO;
-      sc.conv[run] = 2;
-      sc.ru_it[run] = it;
-      sc.ru_thr[run] = fmax(rr, rrt) * ru_factor;
-    }
+  const int lane = threadIdx.x & 63;
+  const int run = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (run >= nruns) return;
+  const int st = sc.status[run];
+  if (!is_active(st)) {
+    if (lane == 0) sc.conv[run] = 0;   // the previous iteration's phase changes are done
+    return;
   }
-  __syncthreads();
-  build_ru_list(sc, nruns);
+  double s[4] = {0, 0, 0, 0};
+  for (int c = lane; c < nchunks; c += 64)
+    for (int k = 0; k < 4; ++k) s[k] += part[((int64_t)run * nchunks + c) * 4 + k];
+  for (int k = 0; k < 4; ++k) s[k] = wsum<double>(s[k]);
+  if (lane != 0) return;
+  sc.conv[run] = 0;
+  const int it = sc.iters[run] + 1;
+  sc.iters[run] = it;
+  const double vn = sc.vn2[run];
+  const double rr = sqrt(s[2] / vn), rrt = sqrt(s[3] / vn);
+  sc.relres[2 * run] = rr;
+  sc.relres[2 * run + 1] = rrt;
+  const double2 rn = make_double2(s[0], s[1]);
+  const double2 ro = sc.rho[run];
+  const bool conv = (rr < tol) && (rrt < tol);
+  const bool bad = !(rn.x != 0.0 || rn.y != 0.0) || !finite2(rn) || !isfinite(rr) || !isfinite(rrt);
+  if (bad && !conv) sc.brk[run] = 1;
+  sc.beta[run] = bad ? make_double2(0, 0) : cdiv<double>(rn, ro);
+  sc.rho_prev[run] = ro;
+  sc.rho[run] = rn;
+  const bool stalled = (st == ST_ACT_LO) && (it - sc.ru_it[run] >= lo_window);
+  if (conv || bad || it >= max_iter || fmax(rr, rrt) < sc.ru_thr[run] || stalled) {
+    sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
+  } else if (st == ST_ACT_HI && narrow_tol > 0.0 && sc.ru_thr[run] >= 0.0 && fmax(rr, rrt) < narrow_tol) {
+    // the residual is small enough for complex64 vectors and operator applications
+    sc.status[run] = ST_ACT_LO;
+    sc.conv[run] = 2;
+    sc.ru_it[run] = it;
+    sc.ru_thr[run] = fmax(rr, rrt) * ru_factor;
+  }
 }
+
+__global__ void __launch_bounds__(256) k_ru_list(BicgScal sc, int32_t nruns) { build_ru_list(sc, nruns); }
 
 __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t nchunks, double* part,
                                             double tol, int32_t max_iter, int32_t max_ru, double ru_factor) {
-  // the partial sums of each replaced run (listed by k_s2): the whole block adds them up and
+  // the partial sums of each replaced run (listed by k_ru_list): the whole block adds them up and
   // leaves the totals in the run's first chunk slot
   __shared__ double red[4][4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -537,8 +544,6 @@ __global__ void __launch_bounds__(256) k_half_stop(BicgScal sc, int32_t ngroups,
       }
     }
   }
-  __syncthreads();
-  build_ru_list(sc, ngroups * n_q * L);
 }
 
 // ------------------------------------------------------------------ host driver
@@ -652,14 +657,16 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
                                  b.upd_part, b.nchunks, st, b.sc.list, b.sc.n_active));
   CBS_TRY(launch_update<double>(s, b.nruns, b.hi.R, b.hi.Q, b.hi.KT, b.sc.alpha, b.sc.status, ST_ACT_HI,
                                 b.upd_part, b.nchunks, st, b.sc.list + b.nruns, b.sc.n_active + 1));
-  hipLaunchKernelGGL(k_s2, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.upd_part, b.tol,
-                     b.max_iter, b.narrow_tol, b.ru_factor, b.lo_window);
+  hipLaunchKernelGGL(k_s2, dim3((b.nruns + 3) / 4), dim3(256), 0, st, b.sc, b.nruns, b.nchunks,
+                     (const double*)b.upd_part, b.tol, b.max_iter, b.narrow_tol, b.ru_factor, b.lo_window);
   CBS_HIP(hipGetLastError());
   if (b.half_stop && b.n_q > 0) {
     hipLaunchKernelGGL(k_half_stop, dim3(1), dim3(256), 0, st, b.sc, b.nruns / (b.n_q * b.L), b.n_q, b.L);
     CBS_HIP(hipGetLastError());
   }
-  // residual replacement of the runs on the list built by k_s2 (and k_half_stop)
+  hipLaunchKernelGGL(k_ru_list, dim3(1), dim3(256), 0, st, b.sc, b.nruns);
+  CBS_HIP(hipGetLastError());
+  // residual replacement of the runs on the list built by k_ru_list
   const int32_t* rul = b.sc.list + 2 * (size_t)b.nruns;
   const int32_t* ruc = b.sc.n_active + 2;
   const int nlr = b.nruns * b.ru_chunks;
