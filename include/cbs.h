@@ -104,7 +104,11 @@ typedef struct {
                            below inner_tol, then complex64 vectors and operator applications
                            with FP64 residual replacement (iterative refinement) to tol */
   int32_t extraction;   /* CBS_RR (default) or CBS_HANKEL */
-  int32_t half_stop;    /* 1: stop all solves once more than half of the nodes converged (Sec. 3.3) */
+  int32_t half_stop;    /* 1: stop all solves at one energy once more than half of the solved
+                           nodes have every right-hand side converged (Sec. 3.3); the stopped
+                           runs keep their iterate (true residual in cbs_info.max_solve_resid).
+                           cbs_solve counts them as finished, cbs_bicg as missing tol.  0
+                           (default): every run to tol. */
   double inner_tol;     /* CBS_MIXED: residual below which a run continues in complex64 (1e-6) */
   int32_t max_refine;   /* cap on FP64 residual replacements per run (60) */
   int32_t chunk;        /* iterations per captured graph between convergence polls (even) */
@@ -187,7 +191,8 @@ int32_t cbs_apply_parts(cbs_system* sys, double E, int32_t n_vec, const double* 
  * device [n_z][L][N] complex128.  iters (host [n_z*L], may be NULL) receives
  * the iteration count of each run and relres (host [2*n_z*L], may be NULL) the
  * final relative residuals (primal, dual).  Returns CBS_ENOCONV if a run
- * missed tol within max_iter (results still written). */
+ * missed tol within max_iter or was stopped by params->half_stop (results
+ * still written). */
 int32_t cbs_bicg(cbs_system* sys, double E, int32_t n_z, const double* z, int32_t n_rhs,
                  const void* V, const cbs_params* params, void* Y, void* Yt,
                  int32_t* iters, double* relres, cbs_info* info, void* stream);

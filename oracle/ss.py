@@ -11,6 +11,7 @@ Sec. 3.1 (Eqs. 6-8, Algorithm 1) and the ring contour of Sec. 3.2:
 The Rayleigh-Ritz variant projects the QEP onto orth(S W1) and solves the
 small QEP densely.  ``bicg`` is the BiCG iteration that solves a system and
 its dual at once (Sec. 3.2, Eq. 11): the dual of P(z) is P(z)^H = P(1/conj z).
+``half_stop_iteration`` is the load-balancing stop of Sec. 3.3.
 """
 from __future__ import annotations
 
@@ -159,3 +160,19 @@ def bicg(apply, apply_dual, b, b_dual, tol=1e-10, max_iter=10000, fixed_iters=No
         p = r + beta * p
         pt = rt + np.conj(beta) * pt
     return x, xt, it, np.linalg.norm(r) / nb, np.linalg.norm(rt) / nbt
+
+
+def half_stop_iteration(node_iters):
+    """Iteration at which the load-balancing rule of Sec. 3.3 stops every solve.
+
+    The solves at all quadrature points advance together, one BiCG iteration each per
+    step, and all stop as soon as more than half of the points have converged.  A point
+    has converged when every right-hand side at it has, so its count is the largest over
+    its right-hand sides: ``node_iters[j]``.  More than half of n points are done after
+    the (n // 2 + 1)-th smallest count.  The iterate a run holds under the rule is its
+    iterate after min(own count, this iteration) steps (the solves do not interact).
+    """
+    counts = sorted(int(c) for c in node_iters)
+    if not counts:
+        raise ValueError("no quadrature points")
+    return counts[len(counts) // 2]

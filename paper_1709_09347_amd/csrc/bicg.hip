@@ -525,7 +525,9 @@ __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t 
 
 // Half-of-the-nodes rule (paper Sec. 3.3): within every group of n_q*L runs, once more
 // than half of the nodes have all their right-hand sides converged, the remaining runs
-// stop (their iterate is still accumulated by a last replacement).
+// stop (their iterate is still accumulated by a last replacement).  A run that changes
+// phase this iteration (conv != 0: its complex64 vectors are written only at the end of
+// the iteration) is stopped at the next one.
 __global__ void __launch_bounds__(256) k_half_stop(BicgScal sc, int32_t ngroups, int32_t n_q, int32_t L) {
   for (int g = threadIdx.x; g < ngroups; g += blockDim.x) {
     int done_nodes = 0;
@@ -537,7 +539,7 @@ __global__ void __launch_bounds__(256) k_half_stop(BicgScal sc, int32_t ngroups,
     if (2 * done_nodes > n_q) {
       for (int r = g * n_q * L; r < (g + 1) * n_q * L; ++r) {
         const int st = sc.status[r];
-        if (st == ST_ACT_LO || st == ST_ACT_HI) {
+        if ((st == ST_ACT_LO || st == ST_ACT_HI) && sc.conv[r] == 0) {
           sc.status[r] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
           sc.halt[r] = 1;
         }

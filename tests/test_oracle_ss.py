@@ -166,3 +166,59 @@ def test_mirrored_nodes_of_real_sources(real_v):
             np.testing.assert_allclose(2 * half.real, sk.real, rtol=0, atol=1e-12 * np.max(np.abs(sk)))
     else:
         assert mirror_err > 1e-3 * scale
+
+
+def test_half_stop_iteration_is_the_first_step_with_more_than_half_done():
+    # brute force of the rule's definition: step the solves together and stop at the first
+    # step after which more than half of the points have converged
+    assert ss.half_stop_iteration([5, 9, 3, 7]) == 7          # 3 of 4 done after step 7
+    assert ss.half_stop_iteration([1, 2, 3, 4, 5]) == 3       # 3 of 5 done after step 3
+    assert ss.half_stop_iteration([4]) == 4
+    assert ss.half_stop_iteration([6, 6, 6, 2]) == 6          # ties: 2 of 4 is not more than half
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        counts = rng.integers(1, 40, size=int(rng.integers(1, 33)))
+        t = 0
+        while 2 * int(np.sum(counts <= t)) <= len(counts):
+            t += 1
+        assert ss.half_stop_iteration(counts) == t
+
+
+def test_half_stop_rule_keeps_the_slowest_point_within_1e_8():
+    # Sec. 4.1: with BiCG to 1e-10 at every point of config 1 (8x8x12), stopping all solves
+    # once more than half of the points converged leaves the slowest runs below 1e-8, and
+    # the eigenvalues still match the dense QEP
+    sysw = W.config(1).systems[0]
+    H = ham.build(sysw)
+    h0, hp, hm = H.blocks_dense()
+    E, L, M, nq = 0.3, 8, 8, 32
+    n = h0.shape[0]
+    Vc = np.ascontiguousarray(W.make_rhs(n, L, 7).T)
+    z1, w1, z2, w2 = ss.quadrature(0.5, nq)
+    A = [qep.P_dense(h0, hp, hm, E, z) for z in z1]
+    AH = [np.ascontiguousarray(a.conj().T) for a in A]
+    full = [[ss.bicg(lambda v: a @ v, lambda v: ah @ v, Vc[:, l], Vc[:, l], tol=1e-10)
+             for l in range(L)] for a, ah in zip(A, AH)]
+    its = np.array([[out[2] for out in row] for row in full])
+    T = ss.half_stop_iteration(its.max(axis=1))
+    assert T < its.max()   # the rule stops some runs early
+    Y1, Y2, worst = [], [], 0.0
+    for j, a in enumerate(A):
+        y1 = np.zeros((n, L), complex)
+        y2 = np.zeros((n, L), complex)
+        for l in range(L):
+            out = full[j][l]
+            if its[j, l] > T:
+                out = ss.bicg(lambda v: a @ v, lambda v: AH[j] @ v, Vc[:, l], Vc[:, l], fixed_iters=T)
+            y1[:, l], y2[:, l] = out[0], out[1]
+            worst = max(worst, out[3], out[4])
+        Y1.append(y1)
+        Y2.append(y2)
+    assert 1e-10 <= worst <= 1e-8
+    S = ss.moments(Y1, Y2, z1, w1, z2, w2, 2 * M)
+    mu = [Vc.conj().T @ s for s in S]
+    res = ss.extract(mu, S[:M], M, 1e-10)
+    lam, psi = ss.rayleigh_ritz(h0, hp, hm, E, S[:M], res[3], res[2], 0.5)
+    ref = qep.solve_dense(h0, hp, hm, E, 0.5, left=False).lam
+    assert len(lam) == len(ref) and qep.match_sets(lam, ref) <= 1e-8
+    assert qep.residuals(h0, hp, hm, E, lam, psi).max() <= 1e-8
