@@ -224,6 +224,18 @@ int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, int32_t n_E
                           const void* const* V, int32_t max_eigs, double* lambda,
                           int32_t* n_eigs, cbs_info* info, void* stream);
 
+/* ---- complex band structure (Sec. 2) ----------------------------------
+ * The complex wave number of each Bloch factor: lambda = exp(i k a) with a the
+ * cell length along the transport direction (N_z h), so
+ * k = (arg lambda - i ln|lambda|) / a on the principal branch, Re k in
+ * [-pi/a, pi/a].  Propagating states (|lambda| = 1) have real k, states decaying
+ * along +z (|lambda| < 1) have Im k > 0.  Scanning E with cbs_solve_batched and
+ * converting each energy's eigenvalues gives the complex band structure.
+ * lambda, k: host [2*n] (re, im pairs; k may alias lambda).  Host arithmetic
+ * only.  CBS_EINVAL (nothing written) if n < 0, cell_length is not a positive
+ * finite number, or a lambda is zero or not finite. */
+int32_t cbs_lambda_to_k(int32_t n, const double* lambda, double cell_length, double* k);
+
 /* ---- adjoint --------------------------------------------------------
  * d lambda_i / d V_loc(r) for eigenpairs sel[k] (host indices into the last
  * cbs_solve's output) = -conj(y_i(r)) x_i(r) / (y_i^H P'(lambda_i) x_i) with

@@ -102,6 +102,13 @@ def free_electron_lambdas(nx, ny, nz, h, p, E) -> np.ndarray:
     return np.concatenate(out)
 
 
+def lambda_to_k(lam, cell_length: float) -> np.ndarray:
+    """Complex wave number of each Bloch factor (Sec. 2: lambda = exp(i k a), a the cell
+    length): k = log(lambda) / (i a) with the principal complex logarithm."""
+    lam = np.asarray(lam, dtype=np.complex128)
+    return np.log(lam) / (1j * cell_length)
+
+
 def in_annulus(lam, lambda_min):
     lam = np.asarray(lam)
     return lam[(np.abs(lam) > lambda_min) & (np.abs(lam) < 1.0 / lambda_min)]

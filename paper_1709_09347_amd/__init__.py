@@ -27,7 +27,7 @@ CBS_RR, CBS_HANKEL = 0, 1
 EXPORTS = [
     "cbs_strerror", "cbs_last_error", "cbs_system_create", "cbs_system_destroy",
     "cbs_system_set_vloc", "cbs_system_npoints", "cbs_system_tiling", "cbs_params_default", "cbs_apply",
-    "cbs_apply_parts", "cbs_bicg", "cbs_solve", "cbs_solve_batched", "cbs_grad_vloc",
+    "cbs_apply_parts", "cbs_bicg", "cbs_solve", "cbs_solve_batched", "cbs_lambda_to_k", "cbs_grad_vloc",
 ]
 
 
@@ -87,6 +87,11 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime with the same soname (libamdhip64.so.7).  Loaded
+        # first, it is the copy the library binds to, so tensors, streams and the library's
+        # kernels share one runtime; loaded after the library, a second runtime would come
+        # in beside the one the library found and the library would see no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.cbs_strerror.restype = ctypes.c_char_p
@@ -119,6 +124,8 @@ def lib():
         L.cbs_solve_batched.restype = i32
         L.cbs_solve_batched.argtypes = [i32, vp, i32, vp, ctypes.POINTER(Params), vp, i32, vp, vp,
                                         vp, vp]
+        L.cbs_lambda_to_k.restype = i32
+        L.cbs_lambda_to_k.argtypes = [i32, vp, dbl, vp]
         L.cbs_grad_vloc.restype = i32
         L.cbs_grad_vloc.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         _LIB = L
@@ -182,6 +189,7 @@ class System:
         self.handle = h_
         self.n = nx * ny * nz
         self.shape = (nx, ny, nz)
+        self.cell_length = nz * h   # a in lambda = exp(i k a)
         self.device = device
         self._keep = []
 
@@ -352,3 +360,21 @@ def solve_batched(systems: List[System], energies, Vs, params: Optional[Params] 
     out = [[lam[s, e, :2 * cnt[s * ne + e]].view(np.complex128).copy() for e in range(ne)]
            for s in range(ns)]
     return out, [infos[i] for i in range(ns * ne)], rc
+
+
+def lambda_to_k(lam, cell_length: float) -> np.ndarray:
+    """Complex wave numbers k of Bloch factors lambda = exp(i k a) (cbs_lambda_to_k)."""
+    lam = _host_c128(lam).reshape(-1)
+    k = np.empty_like(lam)
+    _check(lib().cbs_lambda_to_k(lam.size, lam.ctypes.data, float(cell_length), k.ctypes.data),
+           "cbs_lambda_to_k")
+    return k
+
+
+def cbs_sweep(system: "System", energies, V, params: Optional[Params] = None, max_eigs: int = 512,
+              stream=None):
+    """Complex band structure of one cell over a list of energies: one batched pass
+    (cbs_solve_batched) and k for every eigenvalue.  Returns ([(E, lambda, k)], infos, rc)."""
+    lam, infos, rc = solve_batched([system], energies, [V], params, max_eigs, stream)
+    out = [(float(E), l, lambda_to_k(l, system.cell_length)) for E, l in zip(energies, lam[0])]
+    return out, infos, rc

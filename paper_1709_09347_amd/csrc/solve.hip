@@ -775,3 +775,26 @@ extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, 
   if (worst != CBS_OK) set_error("cbs_solve_batched: %s in at least one (system, energy) pair", cbs_strerror(worst));
   return worst;
 }
+
+// Complex wave number of a Bloch factor (Sec. 2): lambda = exp(i k a) with a the cell
+// length, so k = -i ln(lambda) / a = (arg lambda - i ln|lambda|) / a on the principal
+// branch of the logarithm.
+extern "C" int32_t cbs_lambda_to_k(int32_t n, const double* lambda, double cell_length, double* k) {
+  if (n < 0 || (n > 0 && (!lambda || !k)) || !(cell_length > 0.0) || !std::isfinite(cell_length)) {
+    set_error("cbs_lambda_to_k: bad argument");
+    return CBS_EINVAL;
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    const double re = lambda[2 * i], im = lambda[2 * i + 1];
+    if (!std::isfinite(re) || !std::isfinite(im) || (re == 0.0 && im == 0.0)) {
+      set_error("cbs_lambda_to_k: lambda[%d] is zero or not finite", i);
+      return CBS_EINVAL;
+    }
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    const double re = lambda[2 * i], im = lambda[2 * i + 1];
+    k[2 * i] = std::atan2(im, re) / cell_length;
+    k[2 * i + 1] = -std::log(std::hypot(re, im)) / cell_length;
+  }
+  return CBS_OK;
+}

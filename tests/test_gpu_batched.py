@@ -84,3 +84,39 @@ def test_batched_cfg3_systems_two_energies(cuda):
     assert len(single) == len(lam_b[3][1])
     if len(single):
         assert qep.match_sets(lam_b[3][1], single) <= 1e-10
+
+
+def test_cbs_sweep_cfg1_propagating_k_lie_on_the_bands(cuda):
+    # Sec. 2 and the accuracy test of Sec. 4.1: scan E over config 1 (8x8x12, projectors) in
+    # one batched pass, take k of every Bloch factor (cbs_lambda_to_k), and check that each
+    # propagating state's real k puts E on a band of the Hermitian H(k) = H0 + e^{ika} H+ +
+    # e^{-ika} H-; the eigenvalues equal the dense QEP where it is computed
+    import torch
+    import paper_1709_09347_amd as cbs
+    sysw = W.config(1).systems[0]
+    H = ham.build(sysw)
+    h0, hp, hm = H.blocks_dense()
+    a = sysw.nz * sysw.h
+    L = 8
+    s = cbs.System.from_workload(sysw)
+    assert abs(s.cell_length - a) < 1e-15
+    V = torch.from_numpy(W.make_rhs(sysw.n, L, 5, real=True)).to(cuda)
+    energies = [0.1, 0.3, 0.6, 1.0]
+    sweep, infos, rc = cbs.cbs_sweep(s, energies, V, cbs.default_params(n_rhs=L, n_mom=8))
+    assert rc == 0
+    n_prop = []
+    for (E, lam, k), info in zip(sweep, infos):
+        assert info.nodes_solved == 16
+        np.testing.assert_allclose(k, qep.lambda_to_k(lam, a), rtol=1e-14, atol=1e-15)
+        prop = np.abs(np.abs(lam) - 1) < 1e-6
+        n_prop.append(int(prop.sum()))
+        assert np.all(k[~prop].imag != 0)
+        for kk in k[prop]:
+            assert abs(kk.imag) < 1e-7
+            ev = np.linalg.eigvalsh(h0 + np.exp(1j * kk.real * a) * hp + np.exp(-1j * kk.real * a) * hm)
+            assert np.min(np.abs(ev - E)) < 1e-7, (E, kk)
+        if E in (0.6, 1.0):
+            ref = qep.solve_dense(h0, hp, hm, E, 0.5, left=False).lam
+            assert len(lam) == len(ref) and qep.match_sets(lam, ref) <= 1e-8
+    print("propagating states per energy", dict(zip(energies, n_prop)))
+    assert n_prop[1] == 0 and min(n_prop[0], n_prop[2], n_prop[3]) >= 2

@@ -7,7 +7,10 @@
   closed under lambda -> 1/conj(lambda); real symmetric blocks add conj;
 * residual ||P(lambda) x|| / ||x|| <= 1e-10;
 * propagating modes: for |lambda| = 1, E is an eigenvalue of the Hermitian
-  H(k) = H0 + lambda H+ + conj(lambda) H- (the paper's accuracy test, Sec. 4.1).
+  H(k) = H0 + lambda H+ + conj(lambda) H- (the paper's accuracy test, Sec. 4.1);
+* k of lambda = exp(i k a): inverse of the exponential on the strip
+  -pi/a < Re k <= pi/a, decaying states (|lambda| < 1) have Im k > 0, and on a
+  free chain the propagating k lie on the finite-difference band.
 """
 import numpy as np
 import pytest
@@ -87,3 +90,32 @@ def test_annulus_is_strict():
     lam = np.array([0.5, 0.5000001, 2.0, 1.9999999, 1.0])
     got = qep.in_annulus(lam, 0.5)
     assert list(got) == [0.5000001, 1.9999999, 1.0]
+
+
+def test_lambda_to_k_inverts_the_bloch_factor():
+    rng = np.random.default_rng(4)
+    a = 4.8
+    k = rng.uniform(-np.pi / a, np.pi / a, 200) * 0.999 + 1j * rng.uniform(-1.5, 1.5, 200)
+    lam = np.exp(1j * k * a)
+    np.testing.assert_allclose(qep.lambda_to_k(lam, a), k, rtol=0, atol=1e-12)
+    # decaying along +z (|lambda| < 1) means Im k > 0; |lambda| = 1 means real k
+    got = qep.lambda_to_k(np.array([0.5, 0.5j, 2.0, 1j]), a)
+    assert got[0].imag > 0 and got[1].imag > 0 and got[2].imag < 0 and got[3].imag == 0
+    assert abs(got[1].real - np.pi / 2 / a) < 1e-15 and abs(got[3].real - np.pi / 2 / a) < 1e-15
+
+
+@pytest.mark.parametrize("E", [0.4, 1.3])
+def test_lambda_to_k_of_a_free_chain_lies_on_the_band(E):
+    # one transverse mode (nx = ny = 1): mu = exp(i theta) with E = eps(theta) and
+    # lambda = mu^nz, so k h equals theta up to a multiple of 2 pi / nz
+    nz, h, p = 12, 0.4, 4
+    lam = qep.free_electron_lambdas(1, 1, nz, h, p, E)
+    prop = lam[np.abs(np.abs(lam) - 1) < 1e-10]
+    assert len(prop) == 2
+    k = qep.lambda_to_k(prop, nz * h)
+    assert np.max(np.abs(k.imag)) < 1e-10
+    assert abs(k[0].real + k[1].real) < 1e-10      # +k and -k
+    shifts = 2 * np.pi * np.arange(nz) / nz
+    for kk in k.real:
+        eps = qep.dispersion_1d(p, h, kk * h + shifts)
+        assert np.min(np.abs(eps - E)) < 1e-10
