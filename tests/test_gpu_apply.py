@@ -93,3 +93,12 @@ def test_apply_rejects_bad_input(cuda):
         s.apply(0.1, [1.0, 0.0], x)
     with pytest.raises(cbs.CbsError):
         cbs.System(4, 4, 1, 0.3, 8, np.zeros(16))   # nz < p
+
+
+@pytest.mark.parametrize("cfg,E", [(4, -0.4), (5, -0.6)])
+def test_apply_large_cells_full_size(cuda, cfg, E):
+    # the two large cells (96x96x32 with 384 atoms, 160x160x48 with 1024 atoms) at their
+    # solve energies, every output point against the sparse oracle
+    sysw = W.config(cfg).systems[0]
+    _check(sysw, E, 2, cuda, seed=5)
+    _check(sysw, E, 2, cuda, seed=6, dtype="c64")

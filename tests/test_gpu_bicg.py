@@ -86,3 +86,31 @@ def test_bicg_max_iter_reports_noconv(cuda):
     Y, Yt, iters, relres, info, rc = s.bicg(0.7, [2.0 + 0j], V, prm)
     assert rc == cbs.CBS_ENOCONV
     assert iters.max() <= 4 and relres.max() > 1e-10
+
+
+@pytest.mark.parametrize("cfg,E,L", [(4, -0.4, 2), (5, -0.6, 1)])
+def test_bicg_large_cells_iterates_match_the_oracle(cuda, cfg, E, L):
+    # at full size the solves take thousands of iterations, so the device BiCG is capped at
+    # 20 iterations and its iterates (primal and dual) are compared with the oracle's BiCG
+    # after the same 20 steps on the sparse operator: the same recurrences, so only rounding
+    # separates them (residual still ~0.2, no replacement in between)
+    import torch
+    import paper_1709_09347_amd as cbs
+    sysw = W.config(cfg).systems[0]
+    H = ham.build(sysw)
+    z1, _, z2, _ = ss.quadrature(0.5, 32)
+    j = 5
+    V = W.make_rhs(sysw.n, L, 11)
+    s = cbs.System.from_workload(sysw)
+    prm = cbs.default_params(precision=0, max_iter=20)
+    Y, Yt, iters, relres, info, rc = s.bicg(E, z1[[j]], torch.from_numpy(V).to(cuda), prm)
+    assert rc == cbs.CBS_ENOCONV and iters.max() == 20 and iters.min() == 20
+    Y, Yt = Y.cpu().numpy(), Yt.cpu().numpy()
+    for l in range(L):
+        x, xt, it, rr, rrt = ss.bicg(lambda u: H.apply(z1[j], u, E), lambda u: H.apply(z2[j], u, E),
+                                     V[l], V[l], fixed_iters=20)
+        print(f"{sysw.name} rhs {l}: oracle relres {rr:.3e} / {rrt:.3e}, device {relres[0, l, 0]:.3e} / "
+              f"{relres[0, l, 1]:.3e}")
+        assert np.linalg.norm(Y[0, l] - x) <= 1e-10 * np.linalg.norm(x)
+        assert np.linalg.norm(Yt[0, l] - xt) <= 1e-10 * np.linalg.norm(xt)
+        assert abs(relres[0, l, 0] - rr) <= 1e-8 * rr and abs(relres[0, l, 1] - rrt) <= 1e-8 * rrt
