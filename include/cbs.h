@@ -197,6 +197,21 @@ int32_t cbs_bicg(cbs_system* sys, double E, int32_t n_z, const double* z, int32_
                  const void* V, const cbs_params* params, void* Y, void* Yt,
                  int32_t* iters, double* relres, cbs_info* info, void* stream);
 
+/* As cbs_bicg, and also the convergence history of every run (the per-node
+ * residual curves of Sec. 4.1): hist (host [max_rows][n_z*n_rhs][2], primal
+ * then dual) receives the recursive relative residual ||r|| / ||v|| of each run
+ * after iterations stride, 2*stride, ... (row i = iteration (i+1)*stride), as
+ * the solver computes it (complex64 recurrences in the complex64 phase of
+ * CBS_MIXED, the true residual right after a replacement).  Rows past a run's
+ * last iteration, or past max_rows, hold NaN / are not recorded.  The solve is
+ * the same as cbs_bicg's; the device keeps max_rows*runs*2 doubles during the
+ * call.  CBS_EINVAL if stride < 1, max_rows < 1, hist is NULL or
+ * max_rows*runs*2 >= 2^31; otherwise as cbs_bicg. */
+int32_t cbs_bicg_history(cbs_system* sys, double E, int32_t n_z, const double* z, int32_t n_rhs,
+                         const void* V, const cbs_params* params, int32_t stride, int32_t max_rows,
+                         double* hist, void* Y, void* Yt, int32_t* iters, double* relres,
+                         cbs_info* info, void* stream);
+
 /* ---- the whole method at one energy (Algorithm 1 on the ring contour) --
  * V: device [L][N] complex128 right-hand sides (L = params->n_rhs); when every
  * imaginary part is zero and params->conj_nodes is set, half of the nodes are

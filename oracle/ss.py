@@ -120,14 +120,15 @@ def rayleigh_ritz(h0, hp, hm, E, S_low, W1, rank, lambda_min):
     return r.lam, psi
 
 
-def bicg(apply, apply_dual, b, b_dual, tol=1e-10, max_iter=10000, fixed_iters=None):
+def bicg(apply, apply_dual, b, b_dual, tol=1e-10, max_iter=10000, fixed_iters=None, history=None):
     """BiCG for A x = b together with the dual A^H xt = b_dual.
 
     apply(v) = A v, apply_dual(v) = A^H v.  Scalars alpha = (rt^H r)/(pt^H A p),
     beta = (rt_new^H r_new)/(rt^H r); the dual recurrences use conj(alpha),
     conj(beta).  Stops when both relative residuals are below tol, or after
     ``fixed_iters`` iterations when that is given.  Returns (x, xt, iters,
-    relres, relres_dual).
+    relres, relres_dual).  If ``history`` is a list, the pair of relative
+    residuals after every iteration is appended to it.
     """
     x = np.zeros_like(b)
     xt = np.zeros_like(b_dual)
@@ -152,6 +153,8 @@ def bicg(apply, apply_dual, b, b_dual, tol=1e-10, max_iter=10000, fixed_iters=No
         it += 1
         rr = np.linalg.norm(r) / nb
         rrt = np.linalg.norm(rt) / nbt
+        if history is not None:
+            history.append((rr, rrt))
         if fixed_iters is None and rr < tol and rrt < tol:
             break
         rho_new = np.vdot(rt, r)

@@ -27,7 +27,8 @@ CBS_RR, CBS_HANKEL = 0, 1
 EXPORTS = [
     "cbs_strerror", "cbs_last_error", "cbs_system_create", "cbs_system_destroy",
     "cbs_system_set_vloc", "cbs_system_npoints", "cbs_system_tiling", "cbs_params_default", "cbs_apply",
-    "cbs_apply_parts", "cbs_bicg", "cbs_solve", "cbs_solve_batched", "cbs_lambda_to_k", "cbs_grad_vloc",
+    "cbs_apply_parts", "cbs_bicg", "cbs_bicg_history", "cbs_solve", "cbs_solve_batched", "cbs_lambda_to_k",
+    "cbs_grad_vloc",
 ]
 
 
@@ -118,6 +119,9 @@ def lib():
         L.cbs_bicg.restype = i32
         L.cbs_bicg.argtypes = [vp, dbl, i32, vp, i32, vp, ctypes.POINTER(Params), vp, vp, vp, vp,
                                ctypes.POINTER(Info), vp]
+        L.cbs_bicg_history.restype = i32
+        L.cbs_bicg_history.argtypes = [vp, dbl, i32, vp, i32, vp, ctypes.POINTER(Params), i32, i32, vp, vp, vp,
+                                       vp, vp, ctypes.POINTER(Info), vp]
         L.cbs_solve.restype = i32
         L.cbs_solve.argtypes = [vp, dbl, ctypes.POINTER(Params), vp, i32, vp, vp, vp,
                                 ctypes.POINTER(i32), ctypes.POINTER(Info), vp]
@@ -246,8 +250,10 @@ class System:
         return y
 
     # ---- step 1 ------------------------------------------------------------
-    def bicg(self, E: float, z, V, params: Optional[Params] = None, stream=None):
-        """Solve P(z_j) Y = V and P(z_j)^H Yt = V for every node; returns (Y, Yt, iters, relres, info)."""
+    def bicg(self, E: float, z, V, params: Optional[Params] = None, stream=None, history=None):
+        """Solve P(z_j) Y = V and P(z_j)^H Yt = V for every node; returns (Y, Yt, iters, relres, info, rc).
+        history=(stride, max_rows): also returns the residual histories (cbs_bicg_history) as a
+        seventh item, shape [max_rows][n_z][L][2] (NaN past a run's end)."""
         import torch
         params = params or default_params()
         V = V.contiguous()
@@ -259,11 +265,19 @@ class System:
         iters = np.zeros(nz * L_, dtype=np.int32)
         relres = np.zeros(2 * nz * L_, dtype=np.float64)
         info = Info()
-        rc = lib().cbs_bicg(self.handle, float(E), nz, zz.ctypes.data, L_, _ptr(V),
-                            ctypes.byref(params), _ptr(Y), _ptr(Yt), iters.ctypes.data,
-                            relres.ctypes.data, ctypes.byref(info), _stream(stream))
-        _check(rc, "cbs_bicg", ok=(CBS_OK, CBS_ENOCONV))
-        return Y, Yt, iters.reshape(nz, L_), relres.reshape(nz, L_, 2), info, rc
+        if history is None:
+            rc = lib().cbs_bicg(self.handle, float(E), nz, zz.ctypes.data, L_, _ptr(V),
+                                ctypes.byref(params), _ptr(Y), _ptr(Yt), iters.ctypes.data,
+                                relres.ctypes.data, ctypes.byref(info), _stream(stream))
+            _check(rc, "cbs_bicg", ok=(CBS_OK, CBS_ENOCONV))
+            return Y, Yt, iters.reshape(nz, L_), relres.reshape(nz, L_, 2), info, rc
+        stride, rows = int(history[0]), int(history[1])
+        hist = np.zeros((rows, nz, L_, 2), dtype=np.float64)
+        rc = lib().cbs_bicg_history(self.handle, float(E), nz, zz.ctypes.data, L_, _ptr(V),
+                                    ctypes.byref(params), stride, rows, hist.ctypes.data, _ptr(Y), _ptr(Yt),
+                                    iters.ctypes.data, relres.ctypes.data, ctypes.byref(info), _stream(stream))
+        _check(rc, "cbs_bicg_history", ok=(CBS_OK, CBS_ENOCONV))
+        return Y, Yt, iters.reshape(nz, L_), relres.reshape(nz, L_, 2), info, rc, hist
 
     # ---- the whole method ----------------------------------------------------
     def solve(self, E: float, V, params: Optional[Params] = None, max_eigs: int = 512,

@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t 
 // decisions.  The list of runs marked for replacement is built afterwards (k_ru_list).
 __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
                                             double tol, int32_t max_iter, double narrow_tol, double ru_factor,
-                                            int32_t lo_window) {
+                                            int32_t lo_window, double* hist, int32_t hstride, int32_t hrows) {
   const int lane = threadIdx.x & 63;
   const int run = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (run >= nruns) return;
@@ -433,6 +433,11 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
   const double rr = sqrt(s[2] / vn), rrt = sqrt(s[3] / vn);
   sc.relres[2 * run] = rr;
   sc.relres[2 * run + 1] = rrt;
+  if (hist != nullptr && it % hstride == 0 && it / hstride <= hrows) {
+    const int64_t at = ((int64_t)(it / hstride - 1) * nruns + run) * 2;
+    hist[at] = rr;
+    hist[at + 1] = rrt;
+  }
   const double2 rn = make_double2(s[0], s[1]);
   const double2 ro = sc.rho[run];
   const bool conv = (rr < tol) && (rrt < tol);
@@ -660,7 +665,8 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
   CBS_TRY(launch_update<double>(s, b.nruns, b.hi.R, b.hi.Q, b.hi.KT, b.sc.alpha, b.sc.status, ST_ACT_HI,
                                 b.upd_part, b.nchunks, st, b.sc.list + b.nruns, b.sc.n_active + 1));
   hipLaunchKernelGGL(k_s2, dim3((b.nruns + 3) / 4), dim3(256), 0, st, b.sc, b.nruns, b.nchunks,
-                     (const double*)b.upd_part, b.tol, b.max_iter, b.narrow_tol, b.ru_factor, b.lo_window);
+                     (const double*)b.upd_part, b.tol, b.max_iter, b.narrow_tol, b.ru_factor, b.lo_window,
+                     b.hist, b.hist_stride, b.hist_rows);
   CBS_HIP(hipGetLastError());
   if (b.half_stop && b.n_q > 0) {
     hipLaunchKernelGGL(k_half_stop, dim3(1), dim3(256), 0, st, b.sc, b.nruns / (b.n_q * b.L), b.n_q, b.L);
@@ -974,8 +980,13 @@ void configure_solve(BicgSolve& b, const cbs_params* prm) {
 }
 
 // Step-1 solve of one system at one energy, shared by cbs_bicg and cbs_solve.
+__global__ void k_fill_nan(int64_t n, double* p) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = __builtin_nan("");
+}
+
 int32_t solve_nodes(cbs_system* s, double E, const double2* z, int32_t n_z, int32_t L, const double2* V,
-                    const cbs_params* prm, hipStream_t st, NodeSolve& out) {
+                    const cbs_params* prm, hipStream_t st, NodeSolve& out, const HistReq* hist) {
   std::vector<RunCoef> hc;
   node_coefs(z, n_z, L, E, hc);
   RunCoef* coef = nullptr;
@@ -991,11 +1002,23 @@ int32_t solve_nodes(cbs_system* s, double E, const double2* z, int32_t n_z, int3
   b.coef = coef;
   configure_solve(b, prm);
   CBS_TRY(bicg_alloc(b, "bicg"));
+  const size_t hn = hist ? (size_t)hist->rows * nruns * 2 : 0;
+  if (hn > 0) {
+    // rows a run does not reach keep NaN (filled by a kernel: the buffer is not part of a graph)
+    CBS_TRY(ws_get(s->ws, "bicg.hist", hn, &b.hist));
+    hipLaunchKernelGGL(k_fill_nan, dim3((int)std::min<size_t>((hn + 255) / 256, 4096)), dim3(256), 0, st,
+                       (int64_t)hn, b.hist);
+    CBS_HIP(hipGetLastError());
+    b.hist_stride = hist->stride;
+    b.hist_rows = hist->rows;
+  }
   std::vector<BicgSolve*> v{&b};
   CBS_TRY(bicg_run(v, st, prm->chunk, prm->max_iter, &out.ms, prm->profile != 0));
   CBS_TRY(bicg_collect(b, out, st));
+  if (hn > 0) CBS_HIP(hipMemcpyAsync(hist->host, b.hist, hn * sizeof(double), hipMemcpyDeviceToHost, st));
   // the host coefficient array must outlive the asynchronous copy
   CBS_HIP(hipStreamSynchronize(st));
+  if (hn > 0) s->ws.drop("bicg.hist");
   return CBS_OK;
 }
 
@@ -1025,9 +1048,9 @@ int32_t check_params(const cbs_params* p, bool need_moments) {
 
 using namespace cbs;
 
-extern "C" int32_t cbs_bicg(cbs_system* s, double E, int32_t n_z, const double* z, int32_t n_rhs, const void* V,
-                            const cbs_params* prm, void* Y, void* Yt, int32_t* iters, double* relres, cbs_info* info,
-                            void* stream) {
+static int32_t bicg_entry(cbs_system* s, double E, int32_t n_z, const double* z, int32_t n_rhs, const void* V,
+                          const cbs_params* prm, void* Y, void* Yt, int32_t* iters, double* relres, cbs_info* info,
+                          void* stream, const HistReq* hist) {
   if (!s || n_z < 1 || !z || n_rhs < 1 || !V || !Y || !Yt) {
     set_error("cbs_bicg: bad argument");
     return CBS_EINVAL;
@@ -1042,7 +1065,7 @@ extern "C" int32_t cbs_bicg(cbs_system* s, double E, int32_t n_z, const double* 
   CBS_HIP(hipSetDevice(s->device));
   hipStream_t st = (hipStream_t)stream;
   NodeSolve ns;
-  CBS_TRY(solve_nodes(s, E, (const double2*)z, n_z, n_rhs, (const double2*)V, prm, st, ns));
+  CBS_TRY(solve_nodes(s, E, (const double2*)z, n_z, n_rhs, (const double2*)V, prm, st, ns, hist));
   CBS_TRY(split_pairs(s->N, ns.nruns, ns.Y, (double2*)Y, (double2*)Yt, st));
   CBS_HIP(hipStreamSynchronize(st));
   bool noconv = false;
@@ -1081,4 +1104,29 @@ extern "C" int32_t cbs_bicg(cbs_system* s, double E, int32_t n_z, const double* 
     return CBS_ENOCONV;
   }
   return CBS_OK;
+}
+
+extern "C" int32_t cbs_bicg(cbs_system* s, double E, int32_t n_z, const double* z, int32_t n_rhs, const void* V,
+                            const cbs_params* prm, void* Y, void* Yt, int32_t* iters, double* relres, cbs_info* info,
+                            void* stream) {
+  return bicg_entry(s, E, n_z, z, n_rhs, V, prm, Y, Yt, iters, relres, info, stream, nullptr);
+}
+
+// The residual norm of every run along the iterations (the per-node convergence histories
+// of Sec. 4.1), recorded by the iteration's scalar kernel as it computes them.
+extern "C" int32_t cbs_bicg_history(cbs_system* s, double E, int32_t n_z, const double* z, int32_t n_rhs,
+                                    const void* V, const cbs_params* prm, int32_t stride, int32_t max_rows,
+                                    double* hist, void* Y, void* Yt, int32_t* iters, double* relres,
+                                    cbs_info* info, void* stream) {
+  if (stride < 1 || max_rows < 1 || !hist || n_z < 1 || n_rhs < 1 ||
+      (int64_t)max_rows * n_z * n_rhs * 2 > ((int64_t)1 << 31)) {
+    set_error("cbs_bicg_history: bad argument (stride >= 1, max_rows >= 1, hist not NULL, "
+              "max_rows * runs * 2 < 2^31)");
+    return CBS_EINVAL;
+  }
+  HistReq h;
+  h.stride = stride;
+  h.rows = max_rows;
+  h.host = hist;
+  return bicg_entry(s, E, n_z, z, n_rhs, V, prm, Y, Yt, iters, relres, info, stream, &h);
 }

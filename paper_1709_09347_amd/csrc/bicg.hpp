@@ -78,6 +78,14 @@ struct BicgSolve {
   double tol = 1e-10, ru_factor = 1e-2, narrow_tol = 0.0;
   int32_t max_iter = 10000, max_ru = 1000, half_stop = 0;
   int32_t lo_window = 300;   // complex64 iterations without a 100x drop before a forced replacement
+  double* hist = nullptr;    // [hist_rows][nruns][2] recursive relative residuals, NULL: not recorded
+  int32_t hist_stride = 0, hist_rows = 0;   // row i holds iteration (i + 1) * hist_stride
+};
+
+// Optional residual-history request of solve_nodes (device buffer owned by the workspace).
+struct HistReq {
+  int32_t stride = 0, rows = 0;
+  double* host = nullptr;    // [rows][nruns][2], receives the rows after the solve
 };
 
 struct NodeSolve {
@@ -97,7 +105,7 @@ int32_t bicg_run(std::vector<BicgSolve*>& solves, hipStream_t user, int32_t chun
 int32_t bicg_collect(BicgSolve& b, NodeSolve& out, hipStream_t st);
 void node_coefs(const double2* z, int32_t n_z, int32_t L, double E, std::vector<RunCoef>& out);
 int32_t solve_nodes(cbs_system* s, double E, const double2* z, int32_t n_z, int32_t L, const double2* V,
-                    const cbs_params* prm, hipStream_t st, NodeSolve& out);
+                    const cbs_params* prm, hipStream_t st, NodeSolve& out, const HistReq* hist = nullptr);
 int32_t split_pairs(int64_t N, int32_t nruns, const Pair<double>* Y, double2* ya, double2* yb, hipStream_t st);
 int32_t check_params(const cbs_params* p, bool need_moments);
 void configure_solve(BicgSolve& b, const cbs_params* prm);
