@@ -979,12 +979,12 @@ void configure_solve(BicgSolve& b, const cbs_params* prm) {
   b.half_stop = prm->half_stop;
 }
 
-// Step-1 solve of one system at one energy, shared by cbs_bicg and cbs_solve.
 __global__ void k_fill_nan(int64_t n, double* p) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = __builtin_nan("");
 }
 
+// Step-1 solve of one system at one energy, shared by cbs_bicg, cbs_bicg_history and cbs_solve.
 int32_t solve_nodes(cbs_system* s, double E, const double2* z, int32_t n_z, int32_t L, const double2* V,
                     const cbs_params* prm, hipStream_t st, NodeSolve& out, const HistReq* hist) {
   std::vector<RunCoef> hc;
