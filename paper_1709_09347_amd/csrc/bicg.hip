@@ -1119,7 +1119,7 @@ extern "C" int32_t cbs_bicg_history(cbs_system* s, double E, int32_t n_z, const 
                                     double* hist, void* Y, void* Yt, int32_t* iters, double* relres,
                                     cbs_info* info, void* stream) {
   if (stride < 1 || max_rows < 1 || !hist || n_z < 1 || n_rhs < 1 ||
-      (int64_t)max_rows * n_z * n_rhs * 2 > ((int64_t)1 << 31)) {
+      (int64_t)max_rows * n_z * n_rhs * 2 >= ((int64_t)1 << 31)) {
     set_error("cbs_bicg_history: bad argument (stride >= 1, max_rows >= 1, hist not NULL, "
               "max_rows * runs * 2 < 2^31)");
     return CBS_EINVAL;
