@@ -221,8 +221,9 @@ int32_t cbs_bicg_history(cbs_system* sys, double E, int32_t n_z, const double* z
  * component real positive.  Eigenvalues are sorted by |ln|lambda||, then by
  * arg lambda.  Returns CBS_ETOOMANY with *n_eigs = needed count when
  * max_eigs is too small; CBS_ERANK when the Hankel rank equals L*M (results
- * written, subspace too small); CBS_ENOCONV when a solve missed tol (results
- * written).  The last solve's eigenpairs stay on the system for
+ * written, subspace too small; also at an energy whose annulus holds no
+ * eigenvalue, where the moments are noise: then *n_eigs = 0); CBS_ENOCONV
+ * when a solve missed tol (results written).  The last solve's eigenpairs stay on the system for
  * cbs_grad_vloc. */
 int32_t cbs_solve(cbs_system* sys, double E, const cbs_params* params, const void* V,
                   int32_t max_eigs, double* lambda, double* resid, void* vecs,

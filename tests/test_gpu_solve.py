@@ -198,3 +198,36 @@ def test_solve_cfg1_half_stop_rule(cuda, precision):
     assert info.iters_max < info_f.iters_max
     assert 1e-10 <= info.max_solve_resid <= 1e-8
     _check_against(ref.lam, lam, vecs, res, H, 0.3, res_bar=1e-8)
+
+
+@pytest.mark.parametrize("E", [0.2, 0.3])
+def test_solve_cfg2_propagating_states_lie_on_bands_of_hk(cuda, E):
+    # Sec. 4.1 compares the real k of the propagating states with the conventional band
+    # structure; at 48x48x32 there is no dense H(k) to diagonalise, but H(k) = H0 + e^{ika} H+
+    # + e^{-ika} H- is Hermitian for real k, so some band of H(k) lies within
+    # ||(H(k) - E) psi|| / ||psi|| of E.  That residual (and the Rayleigh quotient) is taken with
+    # the device operator at the k that cbs_lambda_to_k gives; real blocks make the propagating
+    # states come in pairs +k, -k
+    import torch
+    import paper_1709_09347_amd as cbs
+    sysw = W.config(2).systems[0]
+    a = sysw.nz * sysw.h
+    lam, vecs, res, info, rc = _gpu_solve(sysw, E, cuda, L=16, M=8, precision=1, seed=3002, real_v=True)
+    print(f"E={E}: rc {rc}, rank {info.rank}, |lambda| {np.abs(lam)}")
+    assert rc == 0
+    k = cbs.lambda_to_k(lam, a)
+    prop = np.nonzero(np.abs(np.abs(lam) - 1) < 1e-8)[0]
+    assert len(prop) >= 2   # the energies are chosen where the cell has propagating states
+    kp = np.sort(k[prop].real)
+    assert np.max(np.abs(k[prop].imag)) < 1e-9 and np.max(np.abs(kp + kp[::-1])) < 1e-8
+    s = cbs.System.from_workload(sysw)
+    for i in prop:
+        z = np.exp(1j * k[i].real * a)
+        x = torch.from_numpy(np.ascontiguousarray(vecs[i][None, :])).to(cuda)
+        r = s.apply(E, [z], x).cpu().numpy()[0]
+        hx = s.apply(0.0, [z], x).cpu().numpy()[0]
+        nrm2 = np.vdot(vecs[i], vecs[i]).real
+        rq = np.vdot(vecs[i], hx) / nrm2
+        rel = np.linalg.norm(r) / np.sqrt(nrm2)
+        print(f"  k={k[i].real:+.6f}: ||(H(k)-E) psi||/||psi|| = {rel:.2e}, Rayleigh quotient - E = {rq.real - E:.2e}")
+        assert rel <= 1e-9 and abs(rq.real - E) <= 1e-9 and abs(rq.imag) <= 1e-12
