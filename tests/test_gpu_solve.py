@@ -231,3 +231,18 @@ def test_solve_cfg2_propagating_states_lie_on_bands_of_hk(cuda, E):
         rel = np.linalg.norm(r) / np.sqrt(nrm2)
         print(f"  k={k[i].real:+.6f}: ||(H(k)-E) psi||/||psi|| = {rel:.2e}, Rayleigh quotient - E = {rq.real - E:.2e}")
         assert rel <= 1e-9 and abs(rq.real - E) <= 1e-9 and abs(rq.imag) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_empty_annulus(cuda, precision):
+    # degenerate case: below the bands of config 1 (E = -3 Ha) the dense QEP has no eigenvalue
+    # in the annulus; the solve returns none (the moments are noise at the solve tolerance, so
+    # the return code may be CBS_ERANK), and the vectors output is empty
+    import paper_1709_09347_amd as cbs
+    sysw = W.config(1).systems[0]
+    h0, hp, hm = ham.build(sysw).blocks_dense()
+    assert len(qep.solve_dense(h0, hp, hm, -3.0, 0.5, left=False).lam) == 0
+    lam, vecs, res, info, rc = _gpu_solve(sysw, -3.0, cuda, precision=precision, tol=1e-10)
+    print(f"empty annulus: rc {rc}, rank {info.rank}, sigma ratio {info.sigma_ratio:.2e}")
+    assert rc in (0, cbs.CBS_ERANK) and len(lam) == 0 and info.n_eigs == 0
+    assert vecs is None or len(vecs) == 0
