@@ -11,10 +11,13 @@ Everything here is plain, slow and complex128:
                 Hamiltonian (paper Sec. 2, Eqs. 2-4), dense and sparse
   * ``qep``     the quadratic eigenvalue problem solved densely through a
                 companion linearisation (QZ), the free-electron closed form,
-                pairing / residual / H(k) checks (Eq. 5 selects the annulus)
+                pairing / residual / H(k) checks (Eq. 5 selects the annulus),
+                and k of a Bloch factor lambda = exp(i k a) (Sec. 2)
   * ``ss``      the Sakurai-Sugiura steps in the paper's order (Sec. 3.1,
                 Algorithm 1; ring contour of Sec. 3.2) with dense solves,
-                the Rayleigh-Ritz variant, and a plain BiCG with its dual
+                the Rayleigh-Ritz variant, a plain BiCG with its dual (and its
+                residual history), and the iteration at which the
+                load-balancing rule of Sec. 3.3 stops every solve
   * ``adjoint`` eigenvalue derivatives from left/right eigenvectors
 
 Readings of the paper that the oracle fixes (each is listed in the design
