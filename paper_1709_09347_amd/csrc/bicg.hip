@@ -433,6 +433,7 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
   const double rr = sqrt(s[2] / vn), rrt = sqrt(s[3] / vn);
   sc.relres[2 * run] = rr;
   sc.relres[2 * run + 1] = rrt;
+  // optional convergence history: row it / hstride - 1 holds this iteration's residuals
   if (hist != nullptr && it % hstride == 0 && it / hstride <= hrows) {
     const int64_t at = ((int64_t)(it / hstride - 1) * nruns + run) * 2;
     hist[at] = rr;
