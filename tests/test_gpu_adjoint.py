@@ -25,20 +25,23 @@ def tiny_setup():
     return sysw, (h0, hp, hm), ref, g
 
 
-def _solve(sysw, cuda, E=4.0, L=8):
+def _solve(sysw, cuda, E=4.0, L=8, real_v=False):
     import torch
     import paper_1709_09347_amd as cbs
     s = cbs.System.from_workload(sysw)
-    V = torch.from_numpy(W.make_rhs(sysw.n, L, 3)).to(cuda)
+    V = torch.from_numpy(W.make_rhs(sysw.n, L, 3, real=real_v)).to(cuda)
     prm = cbs.default_params(n_rhs=L, n_mom=8)
     lam, vecs, res, info, rc = s.solve(E, V, prm)
-    assert rc == 0
+    assert rc == 0 and info.nodes_solved == (16 if real_v else 32)
     return s, V, prm, lam
 
 
-def test_grad_vloc_matches_dense(cuda, tiny_setup):
+@pytest.mark.parametrize("real_v", [False, True])
+def test_grad_vloc_matches_dense(cuda, tiny_setup, real_v):
+    # real V: half the nodes solved (the mirrored ones by conjugation); the left vectors are
+    # still the partners' eigenvectors from the extraction, so the gradient is the same
     sysw, (h0, hp, hm), ref, g = tiny_setup
-    s, V, prm, lam = _solve(sysw, cuda)
+    s, V, prm, lam = _solve(sysw, cuda, real_v=real_v)
     sel = list(range(len(lam)))
     G = s.grad_vloc(sel).cpu().numpy()
     for k, l in enumerate(lam):
