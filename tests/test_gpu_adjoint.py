@@ -25,23 +25,24 @@ def tiny_setup():
     return sysw, (h0, hp, hm), ref, g
 
 
-def _solve(sysw, cuda, E=4.0, L=8, real_v=False):
+def _solve(sysw, cuda, E=4.0, L=8, real_v=False, precision=0):
     import torch
     import paper_1709_09347_amd as cbs
     s = cbs.System.from_workload(sysw)
     V = torch.from_numpy(W.make_rhs(sysw.n, L, 3, real=real_v)).to(cuda)
-    prm = cbs.default_params(n_rhs=L, n_mom=8)
+    prm = cbs.default_params(n_rhs=L, n_mom=8, precision=precision)
     lam, vecs, res, info, rc = s.solve(E, V, prm)
     assert rc == 0 and info.nodes_solved == (16 if real_v else 32)
     return s, V, prm, lam
 
 
-@pytest.mark.parametrize("real_v", [False, True])
-def test_grad_vloc_matches_dense(cuda, tiny_setup, real_v):
+@pytest.mark.parametrize("real_v,precision", [(False, 0), (True, 0), (True, 1)])
+def test_grad_vloc_matches_dense(cuda, tiny_setup, real_v, precision):
     # real V: half the nodes solved (the mirrored ones by conjugation); the left vectors are
-    # still the partners' eigenvectors from the extraction, so the gradient is the same
+    # still the partners' eigenvectors from the extraction, so the gradient is the same; in
+    # mixed precision (the bench configuration) the eigenvectors come from the refined solves
     sysw, (h0, hp, hm), ref, g = tiny_setup
-    s, V, prm, lam = _solve(sysw, cuda, real_v=real_v)
+    s, V, prm, lam = _solve(sysw, cuda, real_v=real_v, precision=precision)
     sel = list(range(len(lam)))
     G = s.grad_vloc(sel).cpu().numpy()
     for k, l in enumerate(lam):
