@@ -95,7 +95,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", choices=("both", "fp64", "mixed", "mixed_complex_rhs", "mixed_half_stop"),
                     default="both",
-                    help="time one precision only (profiling); the JSON line needs both")
+                    help="time one leg only (profiling); the default runs every leg, which the JSON "
+                         "line needs")
     ap.add_argument("--iters-cap", type=int, default=0,
                     help="cap BiCG at this many iterations (short runs for counter collection; "
                          "no JSON line)")
