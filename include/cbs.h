@@ -155,11 +155,13 @@ const char* cbs_last_error(void);
 
 /* Uploads the grid, local potential (host [N] double) and projector tables
  * (host, may be NULL) to `device` and builds the point-major projector index.
- * Not timed in a solve.  Errors: CBS_EINVAL (shape), CBS_ENOMEM, CBS_EHIP. */
+ * Not timed in a solve.  Errors: CBS_EINVAL (shape, or a non-finite v_loc,
+ * checked before the device is touched), CBS_ENOMEM, CBS_EHIP. */
 int32_t cbs_system_create(cbs_system** out, int32_t device, const cbs_grid* grid,
                           const double* v_loc, const cbs_proj* proj);
 void cbs_system_destroy(cbs_system* sys);
-/* Replace V_loc (host [N] double); keeps projectors and workspace. */
+/* Replace V_loc (host [N] double); keeps projectors and workspace.
+ * CBS_EINVAL (nothing changed) if a value is not finite. */
 int32_t cbs_system_set_vloc(cbs_system* sys, const double* v_loc);
 int64_t cbs_system_npoints(const cbs_system* sys);
 /* Stencil tiling: tile_y[0] (complex128) and tile_y[1] (complex64) full-x rows per

@@ -219,7 +219,9 @@ class System:
         return int(ty[0]), int(ty[1]), log
 
     def set_vloc(self, v_loc):
-        v = np.ascontiguousarray(np.asarray(v_loc, dtype=np.float64))
+        v = np.ascontiguousarray(np.asarray(v_loc, dtype=np.float64)).reshape(-1)
+        if v.size != self.n:
+            raise ValueError(f"v_loc has {v.size} values, the cell has {self.n} points")
         _check(lib().cbs_system_set_vloc(self.handle, v.ctypes.data), "cbs_system_set_vloc")
 
     # ---- operator -----------------------------------------------------------

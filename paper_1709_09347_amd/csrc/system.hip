@@ -380,6 +380,11 @@ int32_t cbs_system_create(cbs_system** out, int32_t device, const cbs_grid* g, c
     set_error("grid too large");
     return CBS_EINVAL;
   }
+  for (int64_t i = 0; i < N; ++i)
+    if (!std::isfinite(v_loc[i])) {
+      set_error("cbs_system_create: v_loc[%lld] is not finite", (long long)i);
+      return CBS_EINVAL;
+    }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
     (void)hipGetLastError();
@@ -424,6 +429,11 @@ int32_t cbs_system_set_vloc(cbs_system* s, const double* v_loc) {
     set_error("cbs_system_set_vloc: null argument");
     return CBS_EINVAL;
   }
+  for (int64_t i = 0; i < s->N; ++i)
+    if (!std::isfinite(v_loc[i])) {
+      set_error("cbs_system_set_vloc: v_loc[%lld] is not finite", (long long)i);
+      return CBS_EINVAL;
+    }
   CBS_HIP(hipSetDevice(s->device));
   std::vector<float> vf(v_loc, v_loc + s->N);
   CBS_HIP(hipMemcpy(s->vloc64, v_loc, s->N * sizeof(double), hipMemcpyHostToDevice));

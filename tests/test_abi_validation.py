@@ -75,3 +75,14 @@ def test_history_and_batch_sizes_are_checked(cbs):
     assert L.cbs_solve_batched(0, None, 1, E.ctypes.data, ctypes.byref(p), None, 1, None, ctypes.byref(n),
                                None, None) == cbs.CBS_EINVAL
     assert "cbs_solve_batched" in _err(L)
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_system_create_rejects_non_finite_potential(cbs, bad):
+    L = cbs.lib()
+    v = np.zeros(8 * 8 * 12)
+    v[77] = bad
+    h = ctypes.c_void_p()
+    g = cbs.Grid(8, 8, 12, 4, 0.4)
+    assert L.cbs_system_create(ctypes.byref(h), 0, ctypes.byref(g), v.ctypes.data, None) == cbs.CBS_EINVAL
+    assert "v_loc[77]" in _err(L) and not h.value

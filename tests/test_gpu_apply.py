@@ -93,6 +93,15 @@ def test_apply_rejects_bad_input(cuda):
         s.apply(0.1, [1.0, 0.0], x)
     with pytest.raises(cbs.CbsError):
         cbs.System(4, 4, 1, 0.3, 8, np.zeros(16))   # nz < p
+    # a non-finite potential is refused and leaves the cell as it was
+    sysw = W.tiny()
+    bad = sysw.v_loc.copy()
+    bad[3] = np.nan
+    with pytest.raises(cbs.CbsError):
+        s.set_vloc(bad)
+    x = torch.ones((1, s.n), dtype=torch.complex128, device=cuda)
+    y = s.apply(0.1, [1.0 + 0j], x).cpu().numpy()
+    assert np.all(np.isfinite(y))
 
 
 @pytest.mark.parametrize("cfg,E", [(4, -0.4), (5, -0.6)])

@@ -23,7 +23,9 @@ DRIVER = os.path.join(ROOT, "tests", "host", "tables_driver.cpp")
 @pytest.fixture(scope="module")
 def driver(tmp_path_factory):
     exe = str(tmp_path_factory.mktemp("tables") / "tables_driver")
-    subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, DRIVER, "-o", exe], check=True)
+    # address and undefined-behaviour sanitizers on the host builder (CPU code only)
+    subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                    "-fno-sanitize-recover=all", "-I", CSRC, DRIVER, "-o", exe], check=True)
     return exe
 
 
