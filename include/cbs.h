@@ -56,7 +56,10 @@ enum {
   CBS_EBREAKDOWN = -5,  /* BiCG breakdown (zero rho or sigma) */
   CBS_ERANK = -6,       /* Hankel rank reached L*M: subspace too small (results written) */
   CBS_ETOOMANY = -7,    /* more eigenvalues than max_eigs (count written) */
-  CBS_ENONFINITE = -8   /* non-finite moments (a linear solve diverged); no eigenpairs */
+  CBS_ENONFINITE = -8,  /* non-finite moments (a linear solve diverged); no eigenpairs */
+  CBS_EEIG = -9         /* a small dense step of the extraction failed (QR iteration of the
+                           reduced eigenproblem, Cholesky QR of the Ritz basis or the LU of the
+                           linearised projected QEP); no eigenpairs */
 };
 
 enum { CBS_C128 = 0, CBS_C64 = 1 };          /* element type of cbs_apply vectors */
@@ -119,6 +122,12 @@ typedef struct {
                            conj z_j are the complex conjugates, and each mirrored pair adds
                            2 Re(w z^k y) to the moments (Sec. 3.1 Eq. 7 summed in pairs).  Same
                            result, half the linear solves.  0: solve every node. */
+  int32_t block;        /* 1 (default): every right-hand side is its own BiCG run (the paper's
+                           Sec. 3.1 solver).  n_rhs: block BiCG over the n_rhs columns of each node
+                           (block Krylov space of P(z_j) on V, n_rhs x n_rhs coefficient matrices
+                           from block inner products); other values: CBS_EINVAL. */
+  int32_t lo_window;    /* CBS_MIXED: complex64 iterations without a 100x residual drop before a
+                           forced complex128 residual replacement (0: 300) */
 } cbs_params;
 
 /* Per-solve diagnostics. */
@@ -145,6 +154,10 @@ typedef struct {
   double stencil_lo_ms;
   double stencil_lo_bytes;
   int32_t nodes_solved;     /* nodes per circle whose systems were solved: n_q, or n_q/2 with conj_nodes */
+  int32_t restarts;         /* CBS_MIXED: runs whose complex64 phase stopped reducing the true residual
+                               and that restarted BiCG in complex128 (summed over the runs) */
+  int32_t status;           /* return code of this solve: of the call (cbs_solve) or of this
+                               (system, energy) pair (cbs_solve_batched) */
 } cbs_info;
 
 /* ---- errors ---------------------------------------------------------- */
@@ -164,6 +177,10 @@ void cbs_system_destroy(cbs_system* sys);
  * CBS_EINVAL (nothing changed) if a value is not finite. */
 int32_t cbs_system_set_vloc(cbs_system* sys, const double* v_loc);
 int64_t cbs_system_npoints(const cbs_system* sys);
+/* Number of solves whose eigenpairs the system has stored for cbs_grad_vloc so far: it
+ * changes whenever cbs_solve or cbs_solve_batched replaces them.  0 before the first
+ * solve, -1 for a NULL handle. */
+int64_t cbs_system_solve_id(const cbs_system* sys);
 /* Stencil tiling: tile_y[0] (complex128) and tile_y[1] (complex64) full-x rows per
  * workgroup, and the autotuner's timings ("" before the first solve tuned them;
  * CBS_AUTOTUNE=0 keeps the heuristic defaults).  The string lives until the next
@@ -175,7 +192,8 @@ void cbs_params_default(cbs_params* p);
 /* ---- operator (Eq. 4) --------------------------------------------------
  * y_v = P(z_v) x_v for a batch of n_vec vectors (device, [n_vec][N], dtype
  * CBS_C128 or CBS_C64), z host [2*n_vec] (re, im), z_v != 0.  x and y must not
- * overlap.  complex64 runs the single-precision kernels end to end. */
+ * overlap.  complex64 runs the single-precision kernels end to end.  The
+ * staging buffers come from the system's workspace (allocated on first use). */
 int32_t cbs_apply(cbs_system* sys, double E, int32_t n_vec, const double* z,
                   int32_t dtype, const void* x, void* y, void* stream);
 
@@ -236,7 +254,11 @@ int32_t cbs_solve(cbs_system* sys, double E, const cbs_params* params, const voi
  * quadrature nodes, right-hand sides, energies and systems share each BiCG
  * kernel launch.  V[s]: device [L][N_s] complex128.  lambda: host
  * [n_sys][n_E][2*max_eigs]; n_eigs: host [n_sys*n_E]; info: host [n_sys*n_E]
- * (may be NULL).  Error codes as cbs_solve (the worst over all pairs). */
+ * (may be NULL); info[i].status holds each pair's own code.  A pair whose
+ * extraction fails (CBS_ENONFINITE, CBS_EEIG) gets n_eigs = 0 and the other pairs
+ * are still solved.  Returns the most severe pair code (CBS_EBREAKDOWN, then
+ * CBS_ENONFINITE, CBS_EEIG, CBS_ENOCONV, CBS_ETOOMANY, CBS_ERANK), or
+ * CBS_EINVAL / CBS_ENOMEM / CBS_EHIP at once. */
 int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, int32_t n_E,
                           const double* E, const cbs_params* params,
                           const void* const* V, int32_t max_eigs, double* lambda,

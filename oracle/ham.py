@@ -106,11 +106,6 @@ class Hamiltonian:
             y = y + sum((z ** (-w)) * (self.u[w] @ c) for w in (-1, 0, 1))
         return y
 
-    def apply_part(self, part: int, x: np.ndarray) -> np.ndarray:
-        """H0 x (part 0), H+ x (part +1) or H- x (part -1); no energy shift."""
-        h0, hp, hm = self.blocks_sparse()
-        return {0: h0, 1: hp, -1: hm}[part] @ x
-
 
 def build(sys) -> Hamiltonian:
     """Assemble the blocks of one ``workloads.System``."""

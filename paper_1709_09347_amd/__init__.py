@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcbs.so")
 
 CBS_OK, CBS_EINVAL, CBS_ENOMEM, CBS_EHIP, CBS_ENOCONV, CBS_EBREAKDOWN, CBS_ERANK, CBS_ETOOMANY, \
-    CBS_ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+    CBS_ENONFINITE, CBS_EEIG = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 CBS_C128, CBS_C64 = 0, 1
 CBS_FP64, CBS_MIXED = 0, 1
 CBS_RR, CBS_HANKEL = 0, 1
@@ -26,7 +26,8 @@ CBS_RR, CBS_HANKEL = 0, 1
 # every function the header declares
 EXPORTS = [
     "cbs_strerror", "cbs_last_error", "cbs_system_create", "cbs_system_destroy",
-    "cbs_system_set_vloc", "cbs_system_npoints", "cbs_system_tiling", "cbs_params_default", "cbs_apply",
+    "cbs_system_set_vloc", "cbs_system_npoints", "cbs_system_solve_id", "cbs_system_tiling",
+    "cbs_params_default", "cbs_apply",
     "cbs_apply_parts", "cbs_bicg", "cbs_bicg_history", "cbs_solve", "cbs_solve_batched", "cbs_lambda_to_k",
     "cbs_grad_vloc",
 ]
@@ -57,7 +58,8 @@ class Params(ctypes.Structure):
                 ("extraction", ctypes.c_int32), ("half_stop", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("conj_nodes", ctypes.c_int32)]
+                ("conj_nodes", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("lo_window", ctypes.c_int32)]
 
     def __repr__(self):
         return "Params(" + ", ".join(f"{n}={getattr(self, n)}" for n, _ in self._fields_) + ")"
@@ -73,7 +75,8 @@ class Info(ctypes.Structure):
                 ("stencil_launches", ctypes.c_int64), ("stencil_ms", ctypes.c_double),
                 ("stencil_bytes", ctypes.c_double), ("stencil_lo_launches", ctypes.c_int64),
                 ("stencil_lo_ms", ctypes.c_double), ("stencil_lo_bytes", ctypes.c_double),
-                ("nodes_solved", ctypes.c_int32)]
+                ("nodes_solved", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -108,6 +111,8 @@ def lib():
         L.cbs_system_set_vloc.argtypes = [vp, vp]
         L.cbs_system_npoints.restype = i64
         L.cbs_system_npoints.argtypes = [vp]
+        L.cbs_system_solve_id.restype = i64
+        L.cbs_system_solve_id.argtypes = [vp]
         L.cbs_system_tiling.restype = ctypes.c_char_p
         L.cbs_system_tiling.argtypes = [vp, vp]
         L.cbs_params_default.restype = None
@@ -211,6 +216,10 @@ class System:
             self.close()
         except Exception:
             pass
+
+    def solve_id(self) -> int:
+        """Counter of the solves whose eigenpairs the system stored (cbs_system_solve_id)."""
+        return int(lib().cbs_system_solve_id(self.handle))
 
     def tiling(self):
         """(tile_y complex128, tile_y complex64, autotuner log)."""
@@ -332,21 +341,35 @@ def _autograd():
 
         forward solves (cbs_solve) with the given potential; backward calls the adjoint
         kernel (cbs_grad_vloc) with the incoming gradient as weights.  ``select`` maps the
-        sorted eigenvalues (numpy) to the indices to return.
+        sorted eigenvalues (numpy) to the indices to return.  The adjoint reads the
+        eigenpairs the system stored with its last solve; when another solve on the same
+        system came between this forward and its backward (two forwards before one
+        backward, gradcheck), backward solves again with this forward's potential and
+        checks that it reproduces the same eigenvalues (the solve is deterministic).
         """
 
         @staticmethod
         def forward(ctx, v_loc, system, E, V, params, select):
-            system.set_vloc(v_loc.detach().cpu().numpy())
+            v = v_loc.detach().cpu().numpy().astype(np.float64).copy()
+            system.set_vloc(v)
             lam, _, _, _, _ = system.solve(E, V, params, want_vectors=False)
             sel = np.asarray(select(lam), dtype=np.int32)
             ctx.system, ctx.sel, ctx.vdev = system, sel, v_loc.device
+            ctx.v, ctx.E, ctx.V, ctx.params, ctx.lam = v, E, V, params, lam.copy()
+            ctx.solve_id = system.solve_id()
             return torch.from_numpy(lam[sel].copy())
 
         @staticmethod
         def backward(ctx, grad):
+            s = ctx.system
+            if s.solve_id() != ctx.solve_id:
+                s.set_vloc(ctx.v)
+                lam, _, _, _, _ = s.solve(ctx.E, ctx.V, ctx.params, want_vectors=False)
+                if lam.shape != ctx.lam.shape or not np.array_equal(lam, ctx.lam):
+                    raise RuntimeError("CbsEig.backward: the repeated solve did not reproduce the "
+                                       "forward's eigenvalues")
             g = grad.detach().cpu().numpy().astype(np.complex128)
-            v = ctx.system.vjp_vloc(ctx.sel, g)
+            v = s.vjp_vloc(ctx.sel, g)
             return v.to(ctx.vdev), None, None, None, None, None
 
     return CbsEig
@@ -361,7 +384,8 @@ def cbs_eig(v_loc, system: "System", E: float, V, params: Optional[Params] = Non
 
 def solve_batched(systems: List[System], energies, Vs, params: Optional[Params] = None,
                   max_eigs: int = 512, stream=None):
-    """Every (system, energy) pair in one batched pass; returns (lam list-of-lists, infos, rc)."""
+    """Every (system, energy) pair in one batched pass; returns (lam list-of-lists, infos, rc).
+    infos[s * len(energies) + e].status is the code of pair (s, e)."""
     params = params or default_params()
     ns, ne = len(systems), len(energies)
     handles = (ctypes.c_void_p * ns)(*[s.handle for s in systems])
@@ -372,9 +396,13 @@ def solve_batched(systems: List[System], energies, Vs, params: Optional[Params] 
     infos = (Info * (ns * ne))()
     rc = lib().cbs_solve_batched(ns, handles, ne, E.ctypes.data, ctypes.byref(params), vps,
                                  max_eigs, lam.ctypes.data, cnt.ctypes.data, infos, _stream(stream))
-    _check(rc, "cbs_solve_batched", ok=(CBS_OK, CBS_ENOCONV, CBS_ERANK))
-    out = [[lam[s, e, :2 * cnt[s * ne + e]].view(np.complex128).copy() for e in range(ne)]
-           for s in range(ns)]
+    # pair-level codes come back in infos[i].status (a failed pair has no eigenvalues); the
+    # call itself fails only on bad arguments, allocation or HIP errors
+    _check(rc, "cbs_solve_batched", ok=(CBS_OK, CBS_ENOCONV, CBS_ERANK, CBS_EBREAKDOWN, CBS_ENONFINITE,
+                                        CBS_EEIG, CBS_ETOOMANY))
+    out = [[(lam[s, e, :2 * cnt[s * ne + e]].view(np.complex128).copy()
+             if infos[s * ne + e].status != CBS_ETOOMANY else np.zeros(0, dtype=np.complex128))
+            for e in range(ne)] for s in range(ns)]
     return out, [infos[i] for i in range(ns * ne)], rc
 
 

@@ -359,6 +359,7 @@ __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t 
     sc.halt[run] = 0;
     sc.conv[run] = 0;
     sc.ru_it[run] = 0;
+    sc.nrestart[run] = 0;
     sc.ru_thr[run] = 0.0;
     const bool zero = !(s[2] > 0);
     sc.relres[2 * run] = zero ? 0.0 : 1.0;
@@ -512,6 +513,7 @@ __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t 
           // beta = 0 makes the true residual the first search direction)
           st = ST_ACT_HI;
           sc.conv[run] = 1;
+          sc.nrestart[run] += 1;
           sc.ru_thr[run] = -1.0;
           sc.beta[run] = make_double2(0, 0);
         } else if (st == ST_RU_LO) {
@@ -602,6 +604,7 @@ int32_t bicg_alloc(BicgSolve& b, const char* tag) {
   CBS_TRY(ws_get(ws, (t + ".conv").c_str(), R, &b.sc.conv));
   CBS_TRY(ws_get(ws, (t + ".nact").c_str(), 3, &b.sc.n_active));
   CBS_TRY(ws_get(ws, (t + ".ruit").c_str(), R, &b.sc.ru_it));
+  CBS_TRY(ws_get(ws, (t + ".nrst").c_str(), R, &b.sc.nrestart));
   CBS_TRY(ws_get(ws, (t + ".list").c_str(), 3 * R, &b.sc.list));
   return CBS_OK;
 }
@@ -899,14 +902,17 @@ int32_t bicg_collect(BicgSolve& b, NodeSolve& out, hipStream_t st) {
   out.iters.resize(b.nruns);
   out.relres.resize(2 * (size_t)b.nruns);
   out.status.resize(b.nruns);
-  std::vector<int32_t> nru(b.nruns);
+  std::vector<int32_t> nru(b.nruns), nrst(b.nruns);
   CBS_HIP(hipMemcpyAsync(out.iters.data(), b.sc.iters, b.nruns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   CBS_HIP(hipMemcpyAsync(out.relres.data(), b.sc.relres, 2 * b.nruns * sizeof(double), hipMemcpyDeviceToHost, st));
   CBS_HIP(hipMemcpyAsync(out.status.data(), b.sc.status, b.nruns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   CBS_HIP(hipMemcpyAsync(nru.data(), b.sc.nru, b.nruns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CBS_HIP(hipMemcpyAsync(nrst.data(), b.sc.nrestart, b.nruns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   CBS_HIP(hipStreamSynchronize(st));
   out.n_ru = 0;
   for (int v : nru) out.n_ru = std::max(out.n_ru, v);
+  out.restarts = 0;
+  for (int v : nrst) out.restarts += v;
   const char* verbose = getenv("CBS_VERBOSE");
   if (verbose && (verbose[0] == '1' || verbose[0] == '2')) {
     // diagnostics: final states, iteration spread, the slowest runs
@@ -978,6 +984,7 @@ void configure_solve(BicgSolve& b, const cbs_params* prm) {
   b.max_iter = prm->max_iter;
   b.max_ru = std::max(prm->max_refine, 1);
   b.half_stop = prm->half_stop;
+  b.lo_window = prm->lo_window > 0 ? prm->lo_window : 300;
 }
 
 __global__ void k_fill_nan(int64_t n, double* p) {
@@ -1031,7 +1038,8 @@ int32_t check_params(const cbs_params* p, bool need_moments) {
   if (!(p->lambda_min > 0 && p->lambda_min < 1) || p->n_q < 1 || p->n_rhs < 1 || !(p->tol > 0) || p->max_iter < 1 ||
       (p->precision != CBS_FP64 && p->precision != CBS_MIXED) ||
       (p->precision == CBS_MIXED && !(p->inner_tol > 0 && p->inner_tol < 1)) ||
-      (p->conj_nodes != 0 && p->conj_nodes != 1)) {
+      (p->conj_nodes != 0 && p->conj_nodes != 1) || p->lo_window < 0 ||
+      (p->block != 1 && p->block != p->n_rhs)) {
     set_error("invalid solver parameters");
     return CBS_EINVAL;
   }
@@ -1091,6 +1099,7 @@ static int32_t bicg_entry(cbs_system* s, double E, int32_t n_z, const double* z,
     info->iters_mean = sum / ns.nruns;
     info->max_solve_resid = mx;
     info->refine_steps = ns.n_ru;
+    info->restarts = (int32_t)std::min<int64_t>(ns.restarts, INT32_MAX);
     info->t_solve_ms = ns.ms;
     info->matvecs = (int64_t)(2 * sum);
     info->stencil_launches = ns.prof_launches;

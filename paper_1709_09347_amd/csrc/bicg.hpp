@@ -38,6 +38,7 @@ struct BicgScal {
   int32_t* nru;
   int32_t* conv;      // phase change this iteration: 1 widen to complex128, 2 narrow to complex64
   int32_t* ru_it;     // iteration of the last replacement (complex64 stagnation guard)
+  int32_t* nrestart;  // complex64 -> complex128 restarts of the run
   int32_t* n_active;  // [3]: active runs in the complex64 / complex128 phase; runs marked
                       // for residual replacement
   int32_t* list;      // [3][nruns]: the runs of each of those sets, ascending (n_active entries)
@@ -97,6 +98,7 @@ struct NodeSolve {
   int64_t prof_launches = 0, prof_lo_launches = 0;   // complex128 / complex64 stencil
   double prof_ms = 0, prof_bytes = 0, prof_lo_ms = 0, prof_lo_bytes = 0;
   int32_t n_ru = 0;
+  int64_t restarts = 0;   // complex64 -> complex128 restarts, summed over the runs
 };
 
 int32_t bicg_alloc(BicgSolve& b, const char* tag);

@@ -257,6 +257,7 @@ struct cbs_system {
   cbs::LastSolve last;
   int32_t tile_y[2] = {0, 0};       // stencil tile rows per precision (0 = double, 1 = float)
   int32_t tuned = 0;                // tile heights picked by the autotuner
+  int64_t solve_id = 0;             // stored solves so far (see cbs_system_solve_id)
   std::string tune_log;
 };
 

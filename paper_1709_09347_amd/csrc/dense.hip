@@ -13,6 +13,7 @@
 
 #include "cbs_internal.hpp"
 #include "dense.hpp"
+#include "ranking.hpp"
 
 namespace cbs {
 
@@ -333,19 +334,9 @@ __global__ void __launch_bounds__(JWG) k_jacobi_svd(int32_t n, c64* A, int32_t l
     sigma[512 + j] = sqrt(s2);   // scratch area after the output
   }
   __syncthreads();
-  // ranks under a strict total order (a non-finite norm counts as -1, ties by index), so
-  // perm is a permutation of 0..n-1 whatever the values are
-  for (int j = tid; j < n; j += JWG) {
-    const double sj0 = sigma[512 + j];
-    const double sj = isfinite(sj0) ? sj0 : -1.0;
-    int rank = 0;
-    for (int k = 0; k < n; ++k) {
-      const double sk0 = sigma[512 + k];
-      const double sk = isfinite(sk0) ? sk0 : -1.0;
-      rank += (sk > sj || (sk == sj && k < j)) ? 1 : 0;
-    }
-    perm[rank] = j;
-  }
+  // ranks under a strict total order (ranking.hpp), so perm is a permutation of 0..n-1
+  // whatever the values are
+  for (int j = tid; j < n; j += JWG) perm[desc_rank(n, sigma + 512, j)] = j;
   __syncthreads();
   for (int r = tid; r < n; r += JWG) sigma[r] = sigma[512 + perm[r]];
   __syncthreads();

@@ -22,6 +22,7 @@
 #include "bicg.hpp"
 #include "cbs_internal.hpp"
 #include "dense.hpp"
+#include "ranking.hpp"
 
 namespace cbs {
 
@@ -76,34 +77,46 @@ __global__ void __launch_bounds__(256) k_moments(int64_t N, int32_t L, int32_t n
   }
 }
 
-// flag[0] = 1 if any imaginary part of the n values is nonzero (or NaN)
+// flag[0] = 1 if any imaginary part of the n values is nonzero; flag[1] = 1 if any value
+// is not finite
 __global__ void __launch_bounds__(256) k_any_imag(int64_t n, const c64* v, int32_t* flag) {
-  bool any = false;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
-    any = any || !(v[g].y == 0.0);
+  bool any = false, bad = false;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    const c64 x = v[g];
+    any = any || !(x.y == 0.0);
+    bad = bad || !(isfinite(x.x) && isfinite(x.y));
+  }
   if (any) flag[0] = 1;
+  if (bad) flag[1] = 1;
 }
 
-__global__ void k_clear_flag(int32_t* flag) { flag[0] = 0; }
+__global__ void k_clear_flag(int32_t* flag) {
+  flag[0] = 0;
+  flag[1] = 0;
+}
 
 static int32_t launch_grid(int64_t work);
 
 // Quadrature nodes per circle to solve: half of them (0 < theta < pi) when the mirrored
 // nodes can be taken from conjugation (conj_nodes, even n_q, every right-hand side real).
+// Right-hand sides holding a non-finite value are rejected (CBS_EINVAL).
 static int32_t nodes_to_solve(cbs_system* s, const cbs_params* prm, const c64* const* V, int n_v, int64_t count,
                               hipStream_t st, int32_t* nq_solved) {
   *nq_solved = prm->n_q;
-  if (!prm->conj_nodes || prm->n_q % 2 != 0) return CBS_OK;
   int32_t* flag = nullptr;
-  CBS_TRY(ws_get(s->ws, "rhs.imag", 1, &flag));
+  CBS_TRY(ws_get(s->ws, "rhs.imag", 2, &flag));
   hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, st, flag);
   for (int i = 0; i < n_v; ++i)
     hipLaunchKernelGGL(k_any_imag, dim3(launch_grid(count)), dim3(256), 0, st, count, V[i], flag);
   CBS_HIP(hipGetLastError());
-  int32_t h = 1;
-  CBS_HIP(hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  int32_t h[2] = {1, 1};
+  CBS_HIP(hipMemcpyAsync(h, flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   CBS_HIP(hipStreamSynchronize(st));
-  if (h == 0) *nq_solved = prm->n_q / 2;
+  if (h[1] != 0) {
+    set_error("the right-hand sides V hold a non-finite value");
+    return CBS_EINVAL;
+  }
+  if (prm->conj_nodes && prm->n_q % 2 == 0 && h[0] == 0) *nq_solved = prm->n_q / 2;
   return CBS_OK;
 }
 
@@ -310,11 +323,10 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
   std::vector<double> hsig(n);
   CBS_HIP(hipMemcpyAsync(hsig.data(), sig, n * sizeof(double), hipMemcpyDeviceToHost, st));
   CBS_HIP(hipStreamSynchronize(st));
-  for (int i = 0; i < n; ++i)
-    if (!std::isfinite(hsig[i])) {
-      set_error("non-finite singular values of the Hankel matrix (a linear solve diverged)");
-      return CBS_ENONFINITE;
-    }
+  if (!all_finite(n, hsig.data())) {
+    set_error("non-finite singular values of the Hankel matrix (a linear solve diverged)");
+    return CBS_ENONFINITE;
+  }
   int m = 0;
   for (int i = 0; i < n; ++i)
     if (hsig[i] > prm->delta * hsig[0]) ++m;
@@ -449,6 +461,17 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
       CBS_TRY(tall_gemm(N, m, ncand, Qa, N, Xt, m, basis, N, st));
     }
   }
+  int32_t hinfo[4];
+  CBS_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+  CBS_HIP(hipStreamSynchronize(st));
+  if (hinfo[0] != 0) {
+    // info[0] = 1: QR iteration did not converge, 2: singular LU pivot, 3: Cholesky QR of
+    // the Ritz basis lost positive definiteness
+    set_error("extraction: %s", hinfo[0] == 1   ? "QR iteration of the reduced eigenproblem did not converge"
+                                : hinfo[0] == 2 ? "the linearised projected QEP is singular at the shift"
+                                                : "Cholesky QR of the Ritz basis failed");
+    return CBS_EEIG;
+  }
   if (ncand == 0) return CBS_OK;
   // --- normalise, residuals ||P(lambda) psi||, annulus, sorting
   double* norms = nullptr;
@@ -464,8 +487,6 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
   std::vector<double> rn(ncand);
   CBS_TRY(vec_norms(N, ncand, Ppsi, N, norms, false, nullptr, 0, st));
   CBS_HIP(hipMemcpyAsync(rn.data(), norms, ncand * sizeof(double), hipMemcpyDeviceToHost, st));
-  int32_t hinfo[4];
-  CBS_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
   CBS_HIP(hipStreamSynchronize(st));
   if (getenv("CBS_DUMP")) {
     std::string dir = getenv("CBS_DUMP");
@@ -475,10 +496,6 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
       for (int i = 0; i < ncand; ++i) fprintf(f, "%.17g %.17g %.6e\n", cand[i].x, cand[i].y, rn[i]);
       fclose(f);
     }
-  }
-  if (hinfo[0] == 1) {
-    set_error("QR iteration of the reduced eigenproblem did not converge");
-    return CBS_ENOCONV;
   }
   // operator scale for the spurious-pair filter
   double cs = std::fabs(s->fd[0]);
@@ -535,6 +552,7 @@ int32_t store_last(cbs_system* s, double E, const Extracted& ex, hipStream_t st)
   }
   L.n = (int32_t)cnt;
   L.E = E;
+  s->solve_id += 1;
   L.lambda = ex.lam;
   if (cnt) CBS_HIP(hipMemcpyAsync(L.vecs, ex.vecs, cnt * s->N * sizeof(c64), hipMemcpyDeviceToDevice, st));
   return CBS_OK;
@@ -596,6 +614,7 @@ extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, con
     info->t_extract_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() - tmom;
     info->matvecs = (int64_t)(2 * sum);
     info->refine_steps = ns.n_ru;
+    info->restarts = (int32_t)std::min<int64_t>(ns.restarts, INT32_MAX);
     info->stencil_launches = ns.prof_launches;
     info->stencil_ms = ns.prof_ms;
     info->stencil_bytes = ns.prof_bytes;
@@ -604,6 +623,12 @@ extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, con
     info->stencil_lo_bytes = ns.prof_lo_bytes;
     info->nodes_solved = nqs;
   }
+  int32_t rc = CBS_OK;
+  if (cnt > max_eigs) rc = CBS_ETOOMANY;
+  else if (brk) rc = CBS_EBREAKDOWN;
+  else if (noconv) rc = CBS_ENOCONV;
+  else if (ex.rank >= prm->n_rhs * prm->n_mom) rc = CBS_ERANK;
+  if (info) info->status = rc;
   if (cnt > max_eigs) {
     set_error("cbs_solve: %d eigenvalues, output holds %d", cnt, max_eigs);
     return CBS_ETOOMANY;
@@ -679,9 +704,21 @@ extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, 
   const int wave = std::max(1, std::min(n_E, (int)(budget / per_energy)));
   std::vector<c64> z1, w1, z2, w2;
   quadrature(prm->lambda_min, prm->n_q, z1, w1, z2, w2);
+  // overall code: the most severe of the pairs' codes
+  auto severity = [](int32_t rc) {
+    switch (rc) {
+      case CBS_EBREAKDOWN: return 6;
+      case CBS_ENONFINITE: return 5;
+      case CBS_EEIG: return 4;
+      case CBS_ENOCONV: return 3;
+      case CBS_ETOOMANY: return 2;
+      case CBS_ERANK: return 1;
+      default: return 0;
+    }
+  };
   int32_t worst = CBS_OK;
   auto note = [&](int32_t rc) {
-    if (rc != CBS_OK && (worst == CBS_OK || rc == CBS_EBREAKDOWN)) worst = rc;
+    if (rc != CBS_OK && (worst == CBS_OK || severity(rc) > severity(worst))) worst = rc;
   };
   for (int e0 = 0; e0 < n_E; e0 += wave) {
     const int ne = std::min(wave, n_E - e0);
@@ -722,8 +759,20 @@ extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, 
         double tmom = 0;
         auto t0 = std::chrono::steady_clock::now();
         const Pair<double>* Ye = ns.Y + (size_t)e * nq * L * sy->N;
-        int32_t rc = extract(sy, E[e0 + e], prm, (const c64*)V[s], Ye, nq, st, ex, &tmom);
-        if (rc != CBS_OK) return rc;
+        const int32_t rc = extract(sy, E[e0 + e], prm, (const c64*)V[s], Ye, nq, st, ex, &tmom);
+        if (rc == CBS_EHIP || rc == CBS_ENOMEM || rc == CBS_EINVAL) return rc;
+        if (rc != CBS_OK) {
+          // this pair has no eigenpairs (non-finite moments or a failed dense step); the
+          // other pairs go on
+          n_eigs[ie] = 0;
+          if (info) {
+            std::memset(&info[ie], 0, sizeof(cbs_info));
+            info[ie].status = rc;
+            info[ie].nodes_solved = nq;
+          }
+          note(rc);
+          continue;
+        }
         auto t1 = std::chrono::steady_clock::now();
         CBS_TRY(store_last(sy, E[e0 + e], ex, st));
         const int cnt = (int)ex.lam.size();
@@ -754,20 +803,24 @@ extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, 
           in.t_extract_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() - tmom;
           in.matvecs = (int64_t)(2 * sum);
           in.refine_steps = ns.n_ru;
+          in.restarts = (int32_t)std::min<int64_t>(ns.restarts, INT32_MAX);
           in.nodes_solved = nq;
         }
+        int32_t prc = CBS_OK;
         if (cnt > max_eigs) {
-          note(CBS_ETOOMANY);
-          continue;
+          prc = CBS_ETOOMANY;
+        } else {
+          double* out = lambda + (size_t)ie * 2 * max_eigs;
+          for (int k = 0; k < cnt; ++k) {
+            out[2 * k] = ex.lam[k].x;
+            out[2 * k + 1] = ex.lam[k].y;
+          }
+          if (brk) prc = CBS_EBREAKDOWN;
+          else if (noconv) prc = CBS_ENOCONV;
+          else if (ex.rank >= L * prm->n_mom) prc = CBS_ERANK;
         }
-        double* out = lambda + (size_t)ie * 2 * max_eigs;
-        for (int k = 0; k < cnt; ++k) {
-          out[2 * k] = ex.lam[k].x;
-          out[2 * k + 1] = ex.lam[k].y;
-        }
-        if (brk) note(CBS_EBREAKDOWN);
-        else if (noconv) note(CBS_ENOCONV);
-        else if (ex.rank >= L * prm->n_mom) note(CBS_ERANK);
+        if (info) info[ie].status = prc;
+        note(prc);
       }
     }
   }

@@ -334,6 +334,7 @@ const char* cbs_strerror(int32_t code) {
     case CBS_ERANK: return "Hankel rank saturated (subspace too small)";
     case CBS_ETOOMANY: return "more eigenvalues than the output holds";
     case CBS_ENONFINITE: return "non-finite moments";
+    case CBS_EEIG: return "dense eigenvalue step failed";
     default: return "unknown error";
   }
 }
@@ -356,6 +357,8 @@ void cbs_params_default(cbs_params* p) {
   p->max_refine = 60;
   p->chunk = 8;
   p->conj_nodes = 1;
+  p->block = 1;
+  p->lo_window = 0;
 }
 
 int32_t cbs_system_create(cbs_system** out, int32_t device, const cbs_grid* g, const double* v_loc,
@@ -373,6 +376,13 @@ int32_t cbs_system_create(cbs_system** out, int32_t device, const cbs_grid* g, c
   if (g->nx < 1 || g->nx > 256 || g->ny < 1 || g->nz < p || !(g->h > 0)) {
     set_error("grid %dx%dx%d h=%g unsupported (need 1<=nx<=256, ny>=1, nz>=p=%d, h>0)", g->nx, g->ny,
               g->nz, g->h, p);
+    return CBS_EINVAL;
+  }
+  // the stencil stages one complex128 plane of a tile of full x rows (at least one row and
+  // its p halo rows on either side, primal and dual) in LDS
+  if ((size_t)(1 + 2 * p) * g->nx * 2 * 16 > 64 * 1024) {
+    set_error("grid nx=%d too wide for fd_order %d: one stencil tile needs %zu bytes of LDS (64 KB)", g->nx,
+              g->fd_order, (size_t)(1 + 2 * p) * g->nx * 2 * 16);
     return CBS_EINVAL;
   }
   const int64_t N = (int64_t)g->nx * g->ny * g->nz;
@@ -442,6 +452,8 @@ int32_t cbs_system_set_vloc(cbs_system* s, const double* v_loc) {
 }
 
 int64_t cbs_system_npoints(const cbs_system* s) { return s ? s->N : -1; }
+
+int64_t cbs_system_solve_id(const cbs_system* s) { return s ? s->solve_id : -1; }
 
 const char* cbs_system_tiling(const cbs_system* s, int32_t* tile_y) {
   if (!s) return "";

@@ -24,7 +24,8 @@ def _err(L):
 
 @pytest.mark.parametrize("grid,why", [((8, 8, 12, 3, 0.4), "fd_order"), ((8, 8, 12, 10, 0.4), "fd_order"),
                                       ((0, 8, 12, 4, 0.4), "grid"), ((300, 8, 12, 4, 0.4), "grid"),
-                                      ((8, 8, 1, 4, 0.4), "grid"), ((8, 8, 12, 4, 0.0), "grid")])
+                                      ((8, 8, 1, 4, 0.4), "grid"), ((8, 8, 12, 4, 0.0), "grid"),
+                                      ((240, 4, 12, 8, 0.3), "too wide")])
 def test_system_create_rejects_unsupported_grids(cbs, grid, why):
     L = cbs.lib()
     v = np.zeros(max(1, grid[0] * grid[1] * grid[2]))

@@ -115,3 +115,48 @@ def test_grad_rejects_bad_selection(cuda, tiny_setup):
     s, V, prm, lam = _solve(sysw, cuda)
     with pytest.raises(cbs.CbsError):
         s.grad_vloc([len(lam) + 3])
+
+
+def test_gradcheck_amplitudes(cuda, tiny_setup):
+    # torch.autograd.gradcheck of lambda(A) = cbs_eig(sum_a A_a g_a) on the tiny cell: the
+    # adjoint's vector-Jacobian products (real and imaginary part of every eigenvalue) against
+    # gradcheck's own central differences of the device solve.  gradcheck runs all its
+    # forwards before the backward, so backward cannot rely on the system's last solve.
+    # Solves refined to 1e-13 keep the eigenvalue noise (~5e-12) far below eps * atol.
+    import torch
+    import paper_1709_09347_amd as cbs
+    sysw, _, _, g = tiny_setup
+    s, V, prm, lam = _solve(sysw, cuda)
+    prm.tol = 1e-13
+    gt = torch.from_numpy(g)
+
+    def f(a):
+        return cbs.cbs_eig(a @ gt, s, 4.0, V, prm)
+
+    amps = torch.tensor(sysw.amps, dtype=torch.float64, requires_grad=True)
+    assert torch.autograd.gradcheck(f, (amps,), eps=1e-6, atol=1e-5, rtol=1e-4)
+
+
+def test_backward_after_another_forward_on_the_same_system(cuda, tiny_setup):
+    # two cbs_eig calls on one system with different potentials, then the backward of the
+    # first: it must be the gradient at the first potential (the same as a lone
+    # forward + backward there), not at the eigenpairs of the later solve
+    import torch
+    import paper_1709_09347_amd as cbs
+    sysw, _, _, g = tiny_setup
+    s, V, prm, lam = _solve(sysw, cuda)
+    gt = torch.from_numpy(g)
+    a0 = torch.tensor(sysw.amps, dtype=torch.float64)
+
+    def grad_of(a, interleave):
+        a = a.clone().requires_grad_(True)
+        out = cbs.cbs_eig(a @ gt, s, 4.0, V, prm)
+        if interleave:
+            cbs.cbs_eig((1.05 * a0) @ gt, s, 4.0, V, prm)   # another forward in between
+        w = torch.linspace(0.5, 1.5, len(out), dtype=torch.float64)
+        (w * (out.real + 2 * out.imag)).sum().backward()
+        return a.grad.numpy().copy()
+
+    alone = grad_of(a0, False)
+    inter = grad_of(a0, True)
+    np.testing.assert_allclose(inter, alone, rtol=1e-9, atol=1e-12)

@@ -167,3 +167,31 @@ def test_bicg_history_cfg1(cuda, precision):
     assert slowest <= 1e-8
     with pytest.raises(cbs.CbsError):
         s.bicg(E, z1[nodes], Vt, prm, history=(0, 10))
+
+
+def test_mixed_restart_in_complex128_is_taken_and_converges(cuda):
+    # regression test of the complex64 -> complex128 restart (the path whose phase kernel once
+    # read an uninitialised complex64 direction): with a one-iteration window every complex64
+    # iteration is followed by a residual replacement, the true residual cannot halve between
+    # two of them, so every run that narrows restarts BiCG in complex128 from its accumulated
+    # solution.  The restart count is reported and the solutions still meet tol against LU.
+    import torch
+    import paper_1709_09347_amd as cbs
+    sysw = W.tiny(with_proj=True, fd_order=8)
+    h0, hp, hm = ham.build(sysw).blocks_dense()
+    E, L = 4.0, 4
+    z = np.exp(1j * 2 * np.pi * (np.arange(4) + 0.5) / 8) / 0.5
+    Vh = W.make_rhs(sysw.n, L, 11)
+    s = cbs.System.from_workload(sysw)
+    prm = cbs.default_params(n_rhs=L, precision=cbs.CBS_MIXED, inner_tol=1e-4, lo_window=1)
+    Y, Yt, iters, relres, info, rc = s.bicg(E, z, torch.from_numpy(Vh).to(cuda), prm)
+    assert rc == 0
+    assert info.restarts > 0, "no complex64 -> complex128 restart taken"
+    Y, Yt = Y.cpu().numpy(), Yt.cpu().numpy()
+    for j, zj in enumerate(z):
+        P = qep.P_dense(h0, hp, hm, E, zj)
+        Pd = qep.P_dense(h0, hp, hm, E, 1 / np.conj(zj))
+        for l in range(L):
+            v = Vh[l]
+            assert np.linalg.norm(v - P @ Y[j, l]) / np.linalg.norm(v) <= 1e-10
+            assert np.linalg.norm(v - Pd @ Yt[j, l]) / np.linalg.norm(v) <= 1e-10

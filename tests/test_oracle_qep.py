@@ -119,3 +119,20 @@ def test_lambda_to_k_of_a_free_chain_lies_on_the_band(E):
     for kk in k.real:
         eps = qep.dispersion_1d(p, h, kk * h + shifts)
         assert np.min(np.abs(eps - E)) < 1e-10
+
+
+def test_match_sets_negative_controls():
+    # the comparator behind every eigenvalue parity test: equal sets (in any order) give 0,
+    # a set with one value moved gives that value's relative gap, sets of different sizes
+    # give inf, and a duplicate that hides a missing value is caught (greedy one-to-one
+    # matching, not nearest-neighbour distances)
+    a = np.array([0.6 + 0.2j, 1.5 - 0.3j, -0.8 + 0.6j, 0.55j])
+    assert qep.match_sets(a, a[::-1]) == 0.0
+    b = a.copy()
+    b[2] = -0.8 + 0.61j
+    assert abs(qep.match_sets(a, b) - 0.01 / abs(a[2])) < 1e-12
+    assert qep.match_sets(a, a[:3]) == np.inf
+    assert qep.match_sets(a[:3], a) == np.inf
+    dup = np.array([a[0], a[0], a[2], a[3]])
+    assert qep.match_sets(a, dup) > 0.5
+    assert qep.match_sets(a, a * (1 + 1e-9)) <= 1.0000001e-9

@@ -251,8 +251,9 @@ def config(c: int) -> Workload:
         s = make_system(96, 96, 32, 0.3, 8, 384, 1004, 2004, cylinder_radius=12.0,
                         with_proj=True, name="cfg4_96x96x32")
         # unpreconditioned BiCG converges here at E <= ~0 Ha (~1500 iterations at -0.4 Ha,
-        # ~4600 at 0, none in 5000 at 0.2 Ha)
-        return Workload("cfg4", [s], SolveConfig([-0.4]), 3004)
+        # ~2200 at -0.2, ~4600 at 0, none in 5000 at 0.2 Ha); the annulus holds no eigenvalue
+        # at -0.4 Ha, 2 at -0.2 Ha (|lambda| 0.535 and 1.870) and 4 at 0 Ha
+        return Workload("cfg4", [s], SolveConfig([-0.2]), 3004)
     if c == 5:
         s = make_system(160, 160, 48, 0.3, 8, 1024, 1005, 2005, cylinder_radius=20.0,
                         with_proj=True, name="cfg5_160x160x48")
