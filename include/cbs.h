@@ -197,6 +197,21 @@ void cbs_params_default(cbs_params* p);
 int32_t cbs_apply(cbs_system* sys, double E, int32_t n_vec, const double* z,
                   int32_t dtype, const void* x, void* y, void* stream);
 
+/* Allocation-free variant of cbs_apply, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and result as cbs_apply; it calls no hipMalloc or hipFree: its
+ * staging buffers (run coefficients, the two pair-interleaved vector buffers and the
+ * projector coefficients) live in one fixed device array of CBS_APPLY_NOALLOC_BYTES per
+ * device, held from the first cbs_system_create on that device until the process ends.
+ * A call needs, each part rounded up to 256 bytes,
+ *   ceil(n_vec/2) * 112  +  2 * ceil(n_vec/2) * N * b  +  ceil(n_vec/2) * n_atoms * 12 * b
+ * bytes, b = 32 (CBS_C128) or 16 (CBS_C64); a larger call returns CBS_EINVAL before
+ * touching the device.  Every call on one device shares the array and leaves its contents
+ * behind; calls that overlap on one device (several streams or threads) race. */
+#define CBS_APPLY_NOALLOC_BYTES (64u << 20)
+int32_t cbs_apply_noalloc(cbs_system* sys, double E, int32_t n_vec, const double* z,
+                          int32_t dtype, const void* x, void* y, void* stream);
+
 /* y_v = c0_v (H0 - E) x_v + cp_v H+ x_v + cm_v H- x_v, coefficients host
  * [2*n_vec] each (re, im); complex128 only.  The z-split form of cbs_apply,
  * used for Rayleigh-Ritz projections. */

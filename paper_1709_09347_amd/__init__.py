@@ -27,7 +27,7 @@ CBS_RR, CBS_HANKEL = 0, 1
 EXPORTS = [
     "cbs_strerror", "cbs_last_error", "cbs_system_create", "cbs_system_destroy",
     "cbs_system_set_vloc", "cbs_system_npoints", "cbs_system_solve_id", "cbs_system_tiling",
-    "cbs_params_default", "cbs_apply",
+    "cbs_params_default", "cbs_apply", "cbs_apply_noalloc",
     "cbs_apply_parts", "cbs_bicg", "cbs_bicg_history", "cbs_solve", "cbs_solve_batched", "cbs_lambda_to_k",
     "cbs_grad_vloc",
 ]
@@ -119,6 +119,8 @@ def lib():
         L.cbs_params_default.argtypes = [ctypes.POINTER(Params)]
         L.cbs_apply.restype = i32
         L.cbs_apply.argtypes = [vp, dbl, i32, vp, i32, vp, vp, vp]
+        L.cbs_apply_noalloc.restype = i32
+        L.cbs_apply_noalloc.argtypes = [vp, dbl, i32, vp, i32, vp, vp, vp]
         L.cbs_apply_parts.restype = i32
         L.cbs_apply_parts.argtypes = [vp, dbl, i32, vp, vp, vp, vp, vp, vp]
         L.cbs_bicg.restype = i32
@@ -247,6 +249,21 @@ class System:
         dt = {torch.complex128: CBS_C128, torch.complex64: CBS_C64}[x.dtype]
         _check(lib().cbs_apply(self.handle, float(E), nv, zz.ctypes.data, dt, _ptr(x), _ptr(y),
                                _stream(stream)), "cbs_apply")
+        return y
+
+    def apply_noalloc(self, E: float, z, x, y, stream=None):
+        """y_v = P(z_v) x_v into the caller's y without any device allocation
+        (cbs_apply_noalloc: staging in the library's fixed scratch array)."""
+        import torch
+        if not (x.is_contiguous() and y.is_contiguous()) or x.shape != y.shape or x.dtype != y.dtype:
+            raise ValueError("x and y: contiguous tensors of one shape and dtype")
+        zz = _host_c128(z)
+        nv = x.shape[0]
+        if zz.size != nv:
+            raise ValueError("one z per vector")
+        dt = {torch.complex128: CBS_C128, torch.complex64: CBS_C64}[x.dtype]
+        _check(lib().cbs_apply_noalloc(self.handle, float(E), nv, zz.ctypes.data, dt, _ptr(x), _ptr(y),
+                                       _stream(stream)), "cbs_apply_noalloc")
         return y
 
     def apply_parts(self, E: float, c0, cp, cm, x, y=None, stream=None):

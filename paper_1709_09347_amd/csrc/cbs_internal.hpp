@@ -316,6 +316,10 @@ int32_t launch_to_pairs(int64_t N, int32_t nvec, const void* x, void* pairs, hip
 template <typename R>
 int32_t launch_from_pairs(int64_t N, int32_t nvec, const void* pairs, void* y, hipStream_t st);
 
+// Device address of the fixed scratch array of cbs_apply_noalloc on `device` (current),
+// looked up once per device (noalloc.hip).
+int32_t noalloc_scratch(int32_t device, void** out);
+
 // Parts-form apply on complex128 vectors (used by the solver's Rayleigh-Ritz step).
 int32_t apply_parts_dev(cbs_system* s, double E, int32_t n_vec, const double2* c0,
                         const double2* cp, const double2* cm, const double2* x, double2* y,

@@ -402,6 +402,11 @@ int32_t cbs_system_create(cbs_system** out, int32_t device, const cbs_grid* g, c
     return CBS_EHIP;
   }
   CBS_HIP(hipSetDevice(device));
+  {
+    // set-up of cbs_apply_noalloc: the device address of its scratch array on this device
+    void* sp = nullptr;
+    CBS_TRY(noalloc_scratch(device, &sp));
+  }
   cbs_system* s = new cbs_system();
   s->device = device;
   s->nx = g->nx;
