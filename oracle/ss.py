@@ -165,6 +165,51 @@ def bicg(apply, apply_dual, b, b_dual, tol=1e-10, max_iter=10000, fixed_iters=No
     return x, xt, it, np.linalg.norm(r) / nb, np.linalg.norm(rt) / nbt
 
 
+def block_bicg(apply, apply_dual, B, tol=1e-10, max_iter=10000):
+    """Block BiCG (O'Leary's block form of the BiCG of ``bicg``) for A X = B with the dual
+    A^H Xt = B, B of shape [N, L]: the scalars become L x L matrices,
+
+        alpha = (Pt^H A P)^-1 (Rt^H R),   alphat = (Pt^H A P)^-H (Rt^H R)^H
+        X += P alpha,  Xt += Pt alphat,   R -= A P alpha,  Rt -= A^H Pt alphat
+        beta = (Rt^H R)^-1 (Rt^H R)_new,  betat = (Rt^H R)^-H (Rt^H R)_new^H
+        P = R + P beta,  Pt = Rt + Pt betat
+
+    (L = 1 gives ``bicg``).  Stops when every column's primal and dual relative residual is
+    below tol.  apply / apply_dual act on [N, L] blocks.  Returns (X, Xt, iters, relres
+    [L], relres_dual [L])."""
+    X = np.zeros_like(B)
+    Xt = np.zeros_like(B)
+    R = B.copy()
+    Rt = B.copy()
+    P = R.copy()
+    Pt = Rt.copy()
+    nb = np.linalg.norm(B, axis=0)
+    rho = Rt.conj().T @ R
+    it = 0
+    while it < max_iter:
+        Q = apply(P)
+        Qt = apply_dual(Pt)
+        sigma = Pt.conj().T @ Q
+        alpha = np.linalg.solve(sigma, rho)
+        alphat = np.linalg.solve(sigma.conj().T, rho.conj().T)
+        X = X + P @ alpha
+        Xt = Xt + Pt @ alphat
+        R = R - Q @ alpha
+        Rt = Rt - Qt @ alphat
+        it += 1
+        rr = np.linalg.norm(R, axis=0) / nb
+        rrt = np.linalg.norm(Rt, axis=0) / nb
+        if np.all(rr < tol) and np.all(rrt < tol):
+            break
+        rho_new = Rt.conj().T @ R
+        beta = np.linalg.solve(rho, rho_new)
+        betat = np.linalg.solve(rho.conj().T, rho_new.conj().T)
+        rho = rho_new
+        P = R + P @ beta
+        Pt = Rt + Pt @ betat
+    return X, Xt, it, np.linalg.norm(R, axis=0) / nb, np.linalg.norm(Rt, axis=0) / nb
+
+
 def half_stop_iteration(node_iters):
     """Iteration at which the load-balancing rule of Sec. 3.3 stops every solve.
 

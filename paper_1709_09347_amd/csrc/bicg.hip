@@ -343,13 +343,13 @@ __device__ void build_ru_list(BicgScal& sc, int32_t nruns) {
 }
 
 __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
-                                            int32_t start) {
+                                            int32_t start, const double* vref) {
   for (int run = threadIdx.x; run < nruns; run += blockDim.x) {
     double s[4];
     sum_part(part, (int64_t)run * nchunks, nchunks, s);
     sc.rho[run] = make_double2(s[0], s[1]);
     sc.rho_prev[run] = make_double2(s[0], s[1]);
-    sc.vn2[run] = s[2];
+    sc.vn2[run] = (vref != nullptr && vref[run] > 0) ? vref[run] : s[2];
     sc.beta[run] = make_double2(0, 0);
     sc.alpha[run] = make_double2(0, 0);
     sc.xcoef[run] = make_double2(0, 0);
@@ -361,9 +361,12 @@ __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t 
     sc.ru_it[run] = 0;
     sc.nrestart[run] = 0;
     sc.ru_thr[run] = 0.0;
-    const bool zero = !(s[2] > 0);
-    sc.relres[2 * run] = zero ? 0.0 : 1.0;
-    sc.relres[2 * run + 1] = zero ? 0.0 : 1.0;
+    // a zero right-hand side is solved by zero; a non-finite one is not "zero" and ends in
+    // a breakdown at the first scalar test
+    const bool zero = s[2] == 0.0 && s[3] == 0.0;
+    const double vn = sc.vn2[run];
+    sc.relres[2 * run] = zero ? 0.0 : (vn > 0 ? sqrt(s[2] / vn) : 1.0);
+    sc.relres[2 * run + 1] = zero ? 0.0 : (vn > 0 ? sqrt(s[3] / vn) : 1.0);
     sc.status[run] = zero ? ST_DONE : start;
   }
   __syncthreads();
@@ -621,7 +624,7 @@ static int32_t enqueue_init(BicgSolve& b, hipStream_t st) {
                      (const Pair<double>*)b.hi.R, b.upd_part);
   CBS_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_s0, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.nchunks, (const double*)b.upd_part,
-                     (int32_t)ST_ACT_HI);
+                     (int32_t)ST_ACT_HI, b.vn2_ref);
   CBS_HIP(hipGetLastError());
   return CBS_OK;
 }
@@ -1074,7 +1077,15 @@ static int32_t bicg_entry(cbs_system* s, double E, int32_t n_z, const double* z,
   CBS_HIP(hipSetDevice(s->device));
   hipStream_t st = (hipStream_t)stream;
   NodeSolve ns;
-  CBS_TRY(solve_nodes(s, E, (const double2*)z, n_z, n_rhs, (const double2*)V, prm, st, ns, hist));
+  if (prm->block > 1) {
+    if (hist) {
+      set_error("cbs_bicg_history: block BiCG keeps no per-run histories");
+      return CBS_EINVAL;
+    }
+    CBS_TRY(solve_nodes_block(s, E, (const double2*)z, n_z, n_rhs, (const double2*)V, prm, st, ns));
+  } else {
+    CBS_TRY(solve_nodes(s, E, (const double2*)z, n_z, n_rhs, (const double2*)V, prm, st, ns, hist));
+  }
   CBS_TRY(split_pairs(s->N, ns.nruns, ns.Y, (double2*)Y, (double2*)Yt, st));
   CBS_HIP(hipStreamSynchronize(st));
   bool noconv = false;

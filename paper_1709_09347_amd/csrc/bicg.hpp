@@ -68,6 +68,8 @@ struct BicgSolve {
   const double2* V = nullptr;       // [L][N]; run r uses right-hand side r % L
   const double2* Vd = nullptr;      // dual right-hand sides (same indexing), NULL: V
   const RunCoef* coef = nullptr;    // [nruns]
+  const double* vn2_ref = nullptr;  // [nruns] ||v||^2 the residuals are measured against (NULL: the
+                                    // initial residual's; set when solving for a correction)
   bool mixed = false;               // start in the complex64 phase
   BicgVecs<float> lo;               // complex64 phase (mixed only)
   BicgVecs<double> hi;              // complex128 phase (also the FP64 residual buffers)
@@ -108,6 +110,9 @@ int32_t bicg_collect(BicgSolve& b, NodeSolve& out, hipStream_t st);
 void node_coefs(const double2* z, int32_t n_z, int32_t L, double E, std::vector<RunCoef>& out);
 int32_t solve_nodes(cbs_system* s, double E, const double2* z, int32_t n_z, int32_t L, const double2* V,
                     const cbs_params* prm, hipStream_t st, NodeSolve& out, const HistReq* hist = nullptr);
+// Block BiCG over the L columns of each node (block.hip); same output as solve_nodes.
+int32_t solve_nodes_block(cbs_system* s, double E, const double2* z, int32_t n_z, int32_t L, const double2* V,
+                          const cbs_params* prm, hipStream_t st, NodeSolve& out);
 int32_t split_pairs(int64_t N, int32_t nruns, const Pair<double>* Y, double2* ya, double2* yb, hipStream_t st);
 int32_t check_params(const cbs_params* p, bool need_moments);
 void configure_solve(BicgSolve& b, const cbs_params* prm);

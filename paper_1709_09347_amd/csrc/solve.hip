@@ -578,7 +578,10 @@ extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, con
   int32_t nqs = prm->n_q;
   CBS_TRY(nodes_to_solve(s, prm, &Vc, 1, (int64_t)prm->n_rhs * s->N, st, &nqs));
   NodeSolve ns;
-  CBS_TRY(solve_nodes(s, E, z1.data(), nqs, prm->n_rhs, Vc, prm, st, ns));
+  if (prm->block > 1)
+    CBS_TRY(solve_nodes_block(s, E, z1.data(), nqs, prm->n_rhs, Vc, prm, st, ns));
+  else
+    CBS_TRY(solve_nodes(s, E, z1.data(), nqs, prm->n_rhs, Vc, prm, st, ns));
   Extracted ex;
   double tmom = 0;
   auto t0 = std::chrono::steady_clock::now();
@@ -671,6 +674,10 @@ extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, 
     return CBS_EINVAL;
   }
   CBS_TRY(check_params(prm, true));
+  if (prm->block > 1) {
+    set_error("cbs_solve_batched: block BiCG runs per (system, energy) through cbs_solve");
+    return CBS_EINVAL;
+  }
   for (int s = 0; s < n_sys; ++s) {
     if (!systems[s] || !V[s] || systems[s]->device != systems[0]->device) {
       set_error("cbs_solve_batched: null system/V or systems on different devices");

@@ -327,3 +327,22 @@ def test_solve_rejects_nonfinite_right_hand_sides(cuda):
     with pytest.raises(cbs.CbsError) as e:
         s.solve(0.3, torch.from_numpy(Vh).to(cuda), cbs.default_params(n_rhs=8, n_mom=8))
     assert e.value.code == cbs.CBS_EINVAL
+
+
+@pytest.mark.parametrize("which", ["tiny", "cfg1"])
+def test_block_bicg_solve_matches_qz(cuda, which):
+    # the whole method with block BiCG in Step 1 (params.block = L): eigenvalues against the
+    # dense QZ oracle to 1e-8, eigenpair residuals recomputed by the oracle; block = 1 is the
+    # per-column solver itself (the default)
+    import paper_1709_09347_amd as cbs
+    sysw = W.tiny(with_proj=True, fd_order=8) if which == "tiny" else W.config(1).systems[0]
+    E = 4.0 if which == "tiny" else 0.3
+    H = ham.build(sysw)
+    h0, hp, hm = H.blocks_dense()
+    ref = qep.solve_dense(h0, hp, hm, E, 0.5, left=False)
+    lam, vecs, res, info, rc = _gpu_solve(sysw, E, cuda, block=8)
+    print(f"block: rc {rc}, max solve residual {info.max_solve_resid:.2e}, iterations max {info.iters_max} "
+          f"mean {info.iters_mean:.1f}")
+    assert rc == 0
+    _check_against(ref.lam, lam, vecs, res, H, E)
+    assert cbs.default_params().block == 1

@@ -222,3 +222,33 @@ def test_half_stop_rule_keeps_the_slowest_point_within_1e_8():
     ref = qep.solve_dense(h0, hp, hm, E, 0.5, left=False).lam
     assert len(lam) == len(ref) and qep.match_sets(lam, ref) <= 1e-8
     assert qep.residuals(h0, hp, hm, E, lam, psi).max() <= 1e-8
+
+
+def test_block_bicg_matches_lu_and_reduces_to_bicg():
+    # the oracle's block BiCG (O'Leary's recurrences with L x L matrices) against the
+    # definition of the result, LU solves of P(z) X = V and P(z)^H Xt = V; with one column it
+    # is the scalar BiCG, iterate for iterate; a wrong transpose in either dual formula (alphat,
+    # betat) breaks the dual solve, a wrong order of the L x L products the primal one
+    sysw = W.tiny(with_proj=True, fd_order=8)
+    h0, hp, hm = ham.build(sysw).blocks_dense()
+    z1, _, _, _ = ss.quadrature(0.5, 32)
+    B = W.make_rhs(sysw.n, 8, 3).T.copy()
+    for j in (0, 7):
+        A = qep.P_dense(h0, hp, hm, 4.0, z1[j])
+        Ad = qep.P_dense(h0, hp, hm, 4.0, 1 / np.conj(z1[j]))
+        X, Xt, it, rr, rrt = ss.block_bicg(lambda P: A @ P, lambda P: Ad @ P, B, tol=1e-11)
+        assert np.all(rr < 1e-11) and np.all(rrt < 1e-11)
+        nb = np.linalg.norm(B, axis=0)
+        assert np.max(np.linalg.norm(B - A @ X, axis=0) / nb) <= 1e-10
+        assert np.max(np.linalg.norm(B - Ad @ Xt, axis=0) / nb) <= 1e-10
+        ref = np.linalg.solve(A, B)
+        assert np.abs(X - ref).max() <= 1e-8 * np.abs(ref).max()
+        its = [ss.bicg(lambda v: A @ v, lambda v: Ad @ v, B[:, l], B[:, l], tol=1e-11)[2] for l in range(8)]
+        assert it < min(its)   # the block Krylov space grows 8 directions per iteration
+        # one column: the iterates of the scalar recurrences (compared after 30 steps, before
+        # the rounding differences of the two codes grow)
+        x1, xt1, it1, _, _ = ss.block_bicg(lambda P: A @ P, lambda P: Ad @ P, B[:, :1], max_iter=30)
+        x0, xt0, it0, _, _ = ss.bicg(lambda v: A @ v, lambda v: Ad @ v, B[:, 0], B[:, 0], fixed_iters=30)
+        assert it1 == it0 == 30
+        assert np.abs(x1[:, 0] - x0).max() <= 1e-11 * np.abs(x0).max()
+        assert np.abs(xt1[:, 0] - xt0).max() <= 1e-11 * np.abs(xt0).max()
