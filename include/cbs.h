@@ -291,6 +291,36 @@ int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, int32_t n_E
  * finite number, or a lambda is zero or not finite. */
 int32_t cbs_lambda_to_k(int32_t n, const double* lambda, double cell_length, double* k);
 
+/* Branches of the complex band structure: the curves k(E) (Sec. 2; the CBS figures of
+ * Sec. 4.1 and 5) from the k of a scan of increasing energies.  E: host [n_E]; n_k: host
+ * [n_E] counts; k: host [sum n_k][2] (re, im), energy by energy.  Each k is joined to the
+ * open branch whose linear prediction (from its last two points) it is nearest to, Re k
+ * compared modulo 2 pi / cell_length, in increasing order of that distance (a greedy
+ * assignment); a point farther than max_jump (1/bohr) from every prediction starts a new
+ * branch, a branch that takes no point ends.  branch: host [sum n_k] branch ids (0 ..
+ * n_branches - 1, in order of appearance).  Host arithmetic only; CBS_EINVAL if a count
+ * is negative, the energies are not increasing or a value is not finite. */
+int32_t cbs_connect_branches(int32_t n_E, const double* E, const int32_t* n_k, const double* k,
+                             double cell_length, double max_jump, int32_t* branch, int32_t* n_branches);
+
+/* ---- conventional band structure (Sec. 2; the cross-check of Sec. 4.1) --
+ * The lowest n_bands eigenvalues of the Hermitian H(k) = H0 + e^{ika} H+ + e^{-ika} H-
+ * (a = nz h, the cell length) at the real wave numbers k (host [n_k], 1/bohr).  A
+ * propagating Bloch factor lambda = e^{ika} of the QEP at energy E makes E an eigenvalue
+ * of H(k), so these bands check the complex band structure where no dense H(k) can be
+ * diagonalised.  Chebyshev-filtered subspace iteration on the device: a block of n_bands
+ * plus guard vectors, a degree-16 filter per step bounded on [largest Ritz value, a
+ * Lanczos bound of the spectrum], Cholesky QR and Rayleigh-Ritz through a Jacobi SVD; the
+ * operator is cbs_apply_parts's complex128 kernels.  Each band stops when
+ * ||H x - eps x|| <= tol (|eps| + 1); a k takes at most max_iter filter steps.
+ * eps: host [n_k][n_bands], ascending; resid: host [n_k][n_bands] residual norms (may
+ * be NULL); vecs: device [n_k][n_bands][N] complex128 unit eigenvectors (may be NULL);
+ * iters: host [n_k] filter steps (may be NULL).  Returns CBS_ENOCONV when a k missed tol
+ * (that k and the earlier ones written), CBS_EINVAL for n_bands beyond ~200 or the grid
+ * size, CBS_EEIG if the Cholesky QR of a filtered block failed. */
+int32_t cbs_bands(cbs_system* sys, int32_t n_k, const double* k, int32_t n_bands, double tol,
+                  int32_t max_iter, double* eps, double* resid, void* vecs, int32_t* iters, void* stream);
+
 /* ---- adjoint --------------------------------------------------------
  * d lambda_i / d V_loc(r) for eigenpairs sel[k] (host indices into the last
  * cbs_solve's output) = -conj(y_i(r)) x_i(r) / (y_i^H P'(lambda_i) x_i) with

@@ -122,6 +122,27 @@ def hk_distance(h0, hp, hm, E, lam):
     return float(np.min(np.abs(ev - E)))
 
 
+def bands_dense(h0, hp, hm, k, cell_length, n_bands):
+    """The lowest n_bands eigenvalues of the Hermitian H(k) = H0 + e^{ika} H+ + e^{-ika} H-
+    (the conventional band structure at real k; Sec. 2, Sec. 4.1), by LAPACK."""
+    lam = np.exp(1j * k * cell_length)
+    hk = h0 + lam * hp + np.conj(lam) * hm
+    hk = 0.5 * (hk + hk.conj().T)
+    return np.linalg.eigvalsh(hk)[:n_bands]
+
+
+def free_electron_bands(nx, ny, nz, h, p, k, n_bands):
+    """Closed form of the lowest bands of the free finite-difference crystal (V = 0, no
+    projectors): plane waves with transverse phases 2 pi n / N and phase (k a + 2 pi n_z) / nz
+    per grid step along z have the eigenvalues eps_perp + eps_z of the 1-D dispersions."""
+    a = nz * h
+    ex = dispersion_1d(p, h, 2 * np.pi * np.arange(nx) / nx)
+    ey = dispersion_1d(p, h, 2 * np.pi * np.arange(ny) / ny)
+    ez = dispersion_1d(p, h, (k * a + 2 * np.pi * np.arange(nz)) / nz)
+    all_ = (ex[:, None, None] + ey[None, :, None] + ez[None, None, :]).reshape(-1)
+    return np.sort(all_)[:n_bands]
+
+
 def match_sets(a, b):
     """Greedy nearest matching of two eigenvalue sets; returns max relative gap."""
     a = list(np.asarray(a))

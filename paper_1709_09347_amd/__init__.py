@@ -29,6 +29,7 @@ EXPORTS = [
     "cbs_system_set_vloc", "cbs_system_npoints", "cbs_system_solve_id", "cbs_system_tiling",
     "cbs_params_default", "cbs_apply", "cbs_apply_noalloc",
     "cbs_apply_parts", "cbs_bicg", "cbs_bicg_history", "cbs_solve", "cbs_solve_batched", "cbs_lambda_to_k",
+    "cbs_bands", "cbs_connect_branches",
     "cbs_grad_vloc",
 ]
 
@@ -137,6 +138,10 @@ def lib():
                                         vp, vp]
         L.cbs_lambda_to_k.restype = i32
         L.cbs_lambda_to_k.argtypes = [i32, vp, dbl, vp]
+        L.cbs_connect_branches.restype = i32
+        L.cbs_connect_branches.argtypes = [i32, vp, vp, vp, dbl, dbl, vp, ctypes.POINTER(i32)]
+        L.cbs_bands.restype = i32
+        L.cbs_bands.argtypes = [vp, i32, vp, i32, dbl, i32, vp, vp, vp, vp, vp]
         L.cbs_grad_vloc.restype = i32
         L.cbs_grad_vloc.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         _LIB = L
@@ -330,6 +335,25 @@ class System:
         lamc = lam[:2 * m].view(np.complex128).copy()
         return lamc, (vecs[:m] if vecs is not None else None), res[:m].copy(), info, rc
 
+    def bands(self, k, n_bands: int, tol: float = 1e-10, max_iter: int = 400, want_vectors: bool = False,
+              stream=None):
+        """Lowest n_bands eigenvalues of the Hermitian H(k) at real wave numbers k (cbs_bands);
+        returns (eps [n_k, n_bands], resid [n_k, n_bands], vecs [n_k, n_bands, N] | None,
+        iters [n_k], rc)."""
+        import torch
+        kk = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(-1))
+        nk = kk.size
+        eps = np.zeros((nk, n_bands), dtype=np.float64)
+        res = np.zeros((nk, n_bands), dtype=np.float64)
+        it = np.zeros(nk, dtype=np.int32)
+        vecs = torch.empty((nk, n_bands, self.n), dtype=torch.complex128, device=f"cuda:{self.device}") \
+            if want_vectors else None
+        rc = lib().cbs_bands(self.handle, nk, kk.ctypes.data, int(n_bands), float(tol), int(max_iter),
+                             eps.ctypes.data, res.ctypes.data, _ptr(vecs) if vecs is not None else None,
+                             it.ctypes.data, _stream(stream))
+        _check(rc, "cbs_bands", ok=(CBS_OK, CBS_ENOCONV))
+        return eps, res, vecs, it, rc
+
     def grad_vloc(self, sel: Sequence[int], stream=None):
         """d lambda_k / d V_loc for the eigenpairs sel of the last solve: [len(sel), N] complex128."""
         import torch
@@ -432,10 +456,33 @@ def lambda_to_k(lam, cell_length: float) -> np.ndarray:
     return k
 
 
+def connect_branches(energies, ks, cell_length: float, max_jump: float):
+    """Branch ids of the k of each energy (cbs_connect_branches): ks is a list of complex
+    arrays, one per energy (increasing).  Returns (list of int arrays, n_branches)."""
+    E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64))
+    counts = np.ascontiguousarray(np.array([len(k) for k in ks], dtype=np.int32))
+    flat = np.ascontiguousarray(np.concatenate([_host_c128(k).reshape(-1) for k in ks])
+                                if len(ks) else np.zeros(0, np.complex128))
+    br = np.zeros(max(1, flat.size), dtype=np.int32)
+    nb = ctypes.c_int32(0)
+    _check(lib().cbs_connect_branches(E.size, E.ctypes.data, counts.ctypes.data, flat.ctypes.data,
+                                      float(cell_length), float(max_jump), br.ctypes.data, ctypes.byref(nb)),
+           "cbs_connect_branches")
+    out, off = [], 0
+    for c in counts:
+        out.append(br[off:off + c].copy())
+        off += c
+    return out, nb.value
+
+
 def cbs_sweep(system: "System", energies, V, params: Optional[Params] = None, max_eigs: int = 512,
-              stream=None):
-    """Complex band structure of one cell over a list of energies: one batched pass
-    (cbs_solve_batched) and k for every eigenvalue.  Returns ([(E, lambda, k)], infos, rc)."""
+              stream=None, max_jump: Optional[float] = None):
+    """Complex band structure of one cell over increasing energies: one batched pass
+    (cbs_solve_batched), k for every eigenvalue and its branch (cbs_connect_branches; max_jump
+    defaults to a tenth of the zone width 2 pi / a).  Returns ([(E, lambda, k, branch)], infos, rc)."""
     lam, infos, rc = solve_batched([system], energies, [V], params, max_eigs, stream)
-    out = [(float(E), l, lambda_to_k(l, system.cell_length)) for E, l in zip(energies, lam[0])]
+    ks = [lambda_to_k(l, system.cell_length) for l in lam[0]]
+    jump = max_jump if max_jump is not None else 0.2 * np.pi / system.cell_length
+    br, _ = connect_branches(energies, ks, system.cell_length, jump)
+    out = [(float(E), l, k, b) for E, l, k, b in zip(energies, lam[0], ks, br)]
     return out, infos, rc

@@ -1033,3 +1033,87 @@ extern "C" int32_t cbs_lambda_to_k(int32_t n, const double* lambda, double cell_
   }
   return CBS_OK;
 }
+
+// Branches of the complex band structure (Sec. 2; the curves k(E) of the CBS figures of
+// Sec. 4.1 and 5): the k of consecutive energies are joined by a greedy assignment on the
+// distance to each open branch's linear prediction (Re k compared modulo 2 pi / a).
+extern "C" int32_t cbs_connect_branches(int32_t n_E, const double* E, const int32_t* n_k, const double* k,
+                                        double cell_length, double max_jump, int32_t* branch,
+                                        int32_t* n_branches) {
+  if (n_E < 0 || (n_E > 0 && (!E || !n_k)) || !(cell_length > 0.0) || !std::isfinite(cell_length) ||
+      !(max_jump > 0.0) || !n_branches) {
+    set_error("cbs_connect_branches: bad argument");
+    return CBS_EINVAL;
+  }
+  int64_t total = 0;
+  for (int e = 0; e < n_E; ++e) {
+    if (n_k[e] < 0 || !std::isfinite(E[e]) || (e > 0 && !(E[e] > E[e - 1]))) {
+      set_error("cbs_connect_branches: counts must be >= 0 and energies finite and increasing");
+      return CBS_EINVAL;
+    }
+    total += n_k[e];
+  }
+  if (total > 0 && (!k || !branch)) {
+    set_error("cbs_connect_branches: bad argument");
+    return CBS_EINVAL;
+  }
+  for (int64_t i = 0; i < 2 * total; ++i)
+    if (!std::isfinite(k[i])) {
+      set_error("cbs_connect_branches: k[%lld] is not finite", (long long)(i / 2));
+      return CBS_EINVAL;
+    }
+  const double period = 2.0 * M_PI / cell_length;
+  auto wrap = [&](double d) { return d - period * std::floor(d / period + 0.5); };
+  struct Open {
+    int id;
+    double kr, ki, pr, pi, e, pe;   // last point, previous point (pe < -1e300: none)
+  };
+  std::vector<Open> open;
+  int next_id = 0;
+  int64_t off = 0;
+  for (int e = 0; e < n_E; ++e) {
+    const int n = n_k[e];
+    std::vector<int> take(n, -1);
+    std::vector<char> used(open.size(), 0);
+    // candidate pairs (open branch, new point) within max_jump of the prediction
+    struct Cand {
+      double d;
+      int b, p;
+    };
+    std::vector<Cand> cand;
+    for (size_t b = 0; b < open.size(); ++b) {
+      const Open& o = open[b];
+      double qr = o.kr, qi = o.ki;
+      if (o.pe > -1e300) {
+        const double f = (E[e] - o.e) / (o.e - o.pe);
+        qr = o.kr + wrap(o.kr - o.pr) * f;
+        qi = o.ki + (o.ki - o.pi) * f;
+      }
+      for (int p = 0; p < n; ++p) {
+        const double dr = wrap(k[2 * (off + p)] - qr), di = k[2 * (off + p) + 1] - qi;
+        const double d = std::sqrt(dr * dr + di * di);
+        if (d <= max_jump) cand.push_back({d, (int)b, p});
+      }
+    }
+    std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) { return a.d < b.d; });
+    std::vector<Open> nxt;
+    for (const Cand& c : cand) {
+      if (used[c.b] || take[c.p] >= 0) continue;
+      used[c.b] = 1;
+      take[c.p] = open[c.b].id;
+      const Open& o = open[c.b];
+      nxt.push_back({o.id, k[2 * (off + c.p)], k[2 * (off + c.p) + 1], o.kr, o.ki, E[e], o.e});
+    }
+    for (int p = 0; p < n; ++p) {
+      if (take[p] < 0) {
+        take[p] = next_id++;
+        nxt.push_back({take[p], k[2 * (off + p)], k[2 * (off + p) + 1], 0.0, 0.0, E[e], -1e308});
+      }
+      branch[off + p] = take[p];
+    }
+    open.swap(nxt);
+    off += n;
+  }
+  *n_branches = next_id;
+  return CBS_OK;
+}

@@ -108,7 +108,7 @@ def test_cbs_sweep_cfg1_propagating_k_lie_on_the_bands(cuda):
     sweep, infos, rc = cbs.cbs_sweep(s, energies, V, cbs.default_params(n_rhs=L, n_mom=8))
     assert rc == 0
     n_prop = []
-    for (E, lam, k), info in zip(sweep, infos):
+    for (E, lam, k, br), info in zip(sweep, infos):
         assert info.nodes_solved == 16
         np.testing.assert_allclose(k, qep.lambda_to_k(lam, a), rtol=1e-14, atol=1e-15)
         prop = np.abs(np.abs(lam) - 1) < 1e-6

@@ -136,3 +136,18 @@ def test_match_sets_negative_controls():
     dup = np.array([a[0], a[0], a[2], a[3]])
     assert qep.match_sets(a, dup) > 0.5
     assert qep.match_sets(a, a * (1 + 1e-9)) <= 1.0000001e-9
+
+
+@pytest.mark.parametrize("k_frac", [0.0, 0.37, -0.81])
+def test_bands_dense_free_electron_closed_form(k_frac):
+    # the oracle's conventional bands (eigvalsh of the assembled Hermitian H(k)) against the
+    # closed form of the free finite-difference crystal: transverse phases 2 pi n / N and z
+    # phase (k a + 2 pi n_z) / nz per grid step; a sign error in the Bloch phase of H+ or H-
+    # moves every band with n_z != 0
+    sysw = W.free_system(4, 5, 6, 0.45, 4)
+    h0, hp, hm = ham.build(sysw).blocks_dense()
+    a = sysw.nz * sysw.h
+    k = k_frac * np.pi / a
+    got = qep.bands_dense(h0, hp, hm, k, a, 40)
+    want = qep.free_electron_bands(4, 5, 6, 0.45, 2, k, 40)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-11)
