@@ -845,6 +845,12 @@ int32_t bicg_alloc(BicgSolve& b, const char* tag) {
   const int na = s->proj.n_atoms;
   CBS_TRY(ws_get(ws, (t + ".signl").c_str(), R * std::max(na, 1), &b.signl));
   CBS_TRY(ws_get(ws, (t + ".upd").c_str(), R * b.nchunks * 4, &b.upd_part));
+  b.bra_part = nullptr;
+  if (s->bra_tile[0] > 0 || s->bra_tile[1] > 0) {
+    unsigned char* bp = nullptr;
+    CBS_TRY(ws_get(ws, (t + ".brapart").c_str(), bra_tile_part_bytes(s, (int32_t)R), &bp));
+    b.bra_part = bp;
+  }
   b.ru_chunks = (int32_t)(((s->N + KG - 1) / KG + 3) / 4);   // one group per wave
   CBS_TRY(ws_get(ws, (t + ".ru").c_str(), R * b.ru_chunks * 4, &b.ru_part));
   CBS_TRY(ws_get(ws, (t + ".alpha").c_str(), R, &b.sc.alpha));
@@ -916,7 +922,7 @@ static int32_t enqueue_stencil_bra(BicgSolve& b, BicgVecs<T>& v, int32_t need, i
   if (v.ev1) CBS_HIP(hipEventRecord(v.ev1, st));
   if (s->proj.n_atoms > 0)
     CBS_TRY(launch_bra<T>(s, b.nruns, v.Pb[parity & 1], b.coef, b.sc.status, need, v.KT, b.signl, st, true,
-                          l.list, l.count));
+                          l.list, l.count, false, b.bra_part));
   return CBS_OK;
 }
 

@@ -97,6 +97,7 @@ struct BicgSolve {
   double2* signl = nullptr;
   double* upd_part = nullptr;
   double* ru_part = nullptr;
+  void* bra_part = nullptr;   // chunk sums of the chunked bra (NULL: the per-atom bra)
   BicgScal sc{};
   double tol = 1e-10, ru_factor = 1e-2, narrow_tol = 0.0;
   int32_t max_iter = 10000, max_ru = 1000, half_stop = 0;

@@ -204,6 +204,20 @@ int32_t ws_get(Workspace& ws, const char* name, size_t count, T** out) {
 }
 
 // ------------------------------------------------------------- system
+struct ChunkTables {
+  int32_t tp = 0, nchunks = 0, nslots = 0, pl = 0;
+  int32_t* piece_off = nullptr;   // [nchunks+1]
+  int32_t* piece_beg = nullptr;   // [npieces]
+  int32_t* piece_meta = nullptr;  // [npieces] (local slot << 16) | entry count
+  int32_t* slot_off = nullptr;    // [nchunks+1]
+  int32_t* slot_piece = nullptr;  // [nslots+1]
+  int32_t* ent_pt = nullptr;      // [nnz] point within the chunk
+  double* u64 = nullptr;          // [nnz][4]
+  float* u32 = nullptr;
+  int32_t* key_off = nullptr;     // [3*n_atoms+1]
+  int32_t* key_slot = nullptr;    // [nslots]
+};
+
 struct Projector {
   int32_t n_atoms = 0;
   int64_t nnz = 0;
@@ -231,8 +245,14 @@ struct Projector {
   double* grp_u64 = nullptr;     // [nkeys][KG][4]
   float* grp_u32 = nullptr;
   int64_t grp_nkeys = 0;
+  // chunked bra tables (see tables.hpp), one set per chunk length BT_TPS[i]: the entries
+  // of every chunk by key, cut into pieces, at most BT_MAXP pieces per chunk; nslots
+  // (chunk, key) slots in all (0: no tables of that length)
+  ChunkTables bt[2];
 };
-constexpr int KG = 64;   // points per ket group (one wavefront)
+constexpr int KG = 64;        // points per ket group (one wavefront)
+constexpr int BT_TPS[2] = {256, 512};   // points per chunk of the chunked bra
+constexpr int BT_MAXP = 128;             // pieces per chunk of the chunked bra
 
 struct LastSolve {
   int32_t n = 0;
@@ -256,6 +276,11 @@ struct cbs_system {
   cbs::Workspace ws;
   cbs::LastSolve last;
   int32_t tile_y[2] = {0, 0};       // stencil tile rows per precision (0 = double, 1 = float)
+  int32_t bra_nw[2] = {4, 4};       // waves per (atom, 16 runs) of the full-batch bra, per precision
+  int32_t bra_spread[2] = {1, 1};   // 1: consecutive bra workgroups on different XCDs (same runs)
+  int32_t bra_tile[2] = {0, 0};     // full-batch bra: 0 = per atom (MFMA), else runs per chunked workgroup
+  int32_t bra_tp[2] = {1, 1};       // chunked bra: which chunk length (index into BT_TPS)
+  int32_t upd_pts = 2048;           // points per chunk of the residual update (its partial sums)
   int32_t tuned = 0;                // tile heights picked by the autotuner
   int64_t solve_id = 0;             // stored solves so far (see cbs_system_solve_id)
   std::string tune_log;
@@ -293,11 +318,14 @@ int32_t default_tile_y(const cbs_system* s, int32_t bytes_per_pair);
 int32_t autotune_tiles(cbs_system* s, hipStream_t st);
 
 // Nonlocal part: bra (coefficients of every atom) then ket tables.
+// tile_part: scratch of bra_tile_part_bytes(s, nruns) bytes for the chunked bra (used for
+// full batches of P(z) when the tables exist and the autotuner chose it), or NULL.
 template <typename R>
 int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunCoef* coef,
                    const int32_t* status, int32_t need_status, void* kt, double2* signl,
                    hipStream_t st, bool phased, const int32_t* list = nullptr,
-                   const int32_t* count = nullptr, bool short_list = false);
+                   const int32_t* count = nullptr, bool short_list = false, void* tile_part = nullptr);
+size_t bra_tile_part_bytes(const cbs_system* s, int32_t nruns);
 
 // Fused pointwise kernels.
 template <typename R>

@@ -303,6 +303,335 @@ __global__ void __launch_bounds__(64 * NW) k_bra_mfma(BraArgs<R> a) {
   }
 }
 
+// ------------------------------------------------------------- chunked bra
+// The same coefficients as k_bra_mfma, computed chunk by chunk: a workgroup copies the
+// direction of RG runs on TP consecutive points into LDS (one coalesced pass over the
+// vector, instead of a gather per ball entry: the balls overlap, every point lies in
+// about five of them) and contracts every ball entry of the chunk from LDS.  A thread takes
+// one piece (consecutive entries of one key) for one run and sums the sixteen products
+// u_i * (primal, dual; re, im) over its entries; the pieces of a key are then added in
+// order through LDS and each (run, chunk, key) sum is written to the partial array.  The
+// finishing kernel adds a key's chunk sums in chunk order and applies the Bloch phases as
+// k_bra_mfma does.  Workgroups of one chunk (its runs in groups of RG) are consecutive on
+// one XCD, so the chunk's table is read from that XCD's L2.
+template <typename R, typename C>
+struct BraTileArgs {
+  int32_t nruns, nchunks, nslots, need_status, nlogical;
+  int64_t N;
+  const int32_t* piece_off;
+  const int32_t* piece_beg;
+  const int32_t* piece_meta;
+  const int32_t* slot_off;
+  const int32_t* slot_piece;
+  const int32_t* ent_pt;
+  const R* ent_u;
+  const Pair<R>* v;
+  const int32_t* status;
+  const int32_t* list;
+  const int32_t* count;
+  C* part;   // [run][slot][16]: u_i times (primal re, primal im, dual re, dual im), i major
+};
+
+// BT_MAXP x RG threads: thread t takes piece t / RG of the chunk (at most BT_MAXP) for run
+// t % RG of the group, so the RG threads of a piece read the same table entries.  The
+// piece's bounds are requested before the staging barrier, so their latency overlaps the
+// staging loads.
+template <typename R, typename C, int RG, int TP>
+__global__ void __launch_bounds__(BT_MAXP * RG, 4) k_bra_tile(BraTileArgs<R, C> a) {
+  static_assert(BT_MAXP * RG <= 1024, "one piece per thread row");
+  // the staged directions (rows padded by one point against bank conflicts between the
+  // runs of a piece), then in the same space the piece sums
+  constexpr int VB = RG * (TP + 1) * (int)sizeof(Pair<R>);
+  constexpr int SB = BT_MAXP * RG * 16 * (int)sizeof(C);
+  constexpr int LDSB = VB > SB ? VB : SB;
+  static_assert(LDSB <= 160 * 1024, "staging exceeds LDS");
+  constexpr int NT = BT_MAXP * RG;
+  constexpr int EB = 4;   // entries whose table loads are issued together
+  using U4 = typename vec4<R>::T;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LDSB];
+  __shared__ int srun[RG];
+  const int nsl = (a.list != nullptr) ? *a.count : a.nruns;
+  const int ngr = (nsl + RG - 1) / RG;
+  const int nl = min(a.nlogical, ngr * a.nchunks);
+  const int lb = remap_active(blockIdx.x, nl);
+  if (lb < 0) return;
+  const int c = lb / ngr;
+  const int rg = lb - c * ngr;
+  const int tid = threadIdx.x;
+  int any = 0;
+  if (tid < RG) {
+    const int slot = rg * RG + tid;
+    int run = -1;
+    if (slot < nsl) {
+      run = (a.list != nullptr) ? a.list[slot] : slot;
+      if (a.status != nullptr && a.status[run] != a.need_status) run = -1;
+    }
+    srun[tid] = run;
+    any = run >= 0;
+  }
+  if (!__syncthreads_or(any)) return;
+  Pair<R>* vs = reinterpret_cast<Pair<R>*>(lds);
+  const int64_t p0 = (int64_t)c * TP;
+  const int np = (int)min<int64_t>(TP, a.N - p0);
+  const int j = tid % RG, lp = tid / RG;
+  const int run = srun[j];
+  // this thread's piece
+  const int pb = a.piece_off[c];
+  const int npc = a.piece_off[c + 1] - pb;
+  const bool work = lp < npc && run >= 0;
+  int beg = 0, end = 1;
+  if (work) {
+    beg = a.piece_beg[pb + lp];
+    end = beg + (a.piece_meta[pb + lp] & 0xffff);
+  }
+  const U4* ut = reinterpret_cast<const U4*>(a.ent_u);
+  {
+    // every thread's share of the chunk is loaded before any of it is stored (loads are
+    // unconditional, from a valid run and point: rows of empty run slots and points past
+    // the cell's end are staged but never read)
+    constexpr int SPT = RG * TP / NT;
+    static_assert(SPT * NT == RG * TP, "staging covers the chunk");
+    int rows[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) rows[q] = max(srun[(tid + q * NT) / TP], 0);
+    Pair<R> tmp[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int i = tid + q * NT;
+      const int pt = min(i % TP, np - 1);
+      tmp[q] = a.v[(int64_t)rows[q] * a.N + p0 + pt];
+    }
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int i = tid + q * NT;
+      const int jj = i / TP, pt = i - jj * TP;
+      vs[jj * (TP + 1) + pt] = tmp[q];
+    }
+  }
+  __syncthreads();
+  const Pair<R>* vj = vs + j * (TP + 1);
+  C acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0;
+  if (work) {
+    int pts[EB];
+    U4 us[EB];
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
+      const int e = min(beg + q, end - 1);
+      pts[q] = a.ent_pt[e];
+      us[q] = ut[e];
+    }
+    for (int e0 = beg;;) {
+#pragma unroll
+      for (int q = 0; q < EB; ++q) {
+        // entries past the piece (their index clamped to its last entry) add nothing
+        const Pair<R> x = vj[pts[q]];
+        const C w = (e0 + q < end) ? (C)1 : (C)0;
+        const C u4[4] = {w * (C)us[q].x, w * (C)us[q].y, w * (C)us[q].z, w * (C)us[q].w};
+        const C xs[4] = {(C)x.a.x, (C)x.a.y, (C)x.b.x, (C)x.b.y};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[4 * i + k] += u4[i] * xs[k];
+      }
+      e0 += EB;
+      if (e0 >= end) break;
+      // the next batch, indices clamped to the piece
+#pragma unroll
+      for (int q = 0; q < EB; ++q) {
+        const int e = min(e0 + q, end - 1);
+        pts[q] = a.ent_pt[e];
+        us[q] = ut[e];
+      }
+    }
+  }
+  __syncthreads();   // every thread is done with the staged directions
+  C* psum = reinterpret_cast<C*>(lds);   // [local piece][run of the group][16]
+  if (lp < npc) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) psum[(lp * RG + j) * 16 + k] = acc[k];
+  }
+  __syncthreads();
+  const int so = a.slot_off[c];
+  const int nsc = a.slot_off[c + 1] - so;
+  for (int i = tid; i < nsc * RG * 16; i += NT) {
+    const int ls = i / (RG * 16);
+    const int rem = i - ls * (RG * 16);
+    const int jj = rem >> 4, k = rem & 15;
+    const int rr = srun[jj];
+    if (rr < 0) continue;
+    const int g = so + ls;
+    const int q0 = a.slot_piece[g] - pb, q1 = a.slot_piece[g + 1] - pb;
+    C sum = 0;
+    for (int q = q0; q < q1; ++q) sum += psum[(q * RG + jj) * 16 + k];
+    a.part[((int64_t)rr * a.nslots + g) * 16 + k] = sum;
+  }
+}
+
+template <typename R, typename C>
+struct BraFinArgs {
+  int32_t nruns, n_atoms, nslots, need_status, nlogical;
+  const int32_t* key_off;
+  const int32_t* key_slot;
+  const C* part;
+  const R* coeff;
+  const RunCoef* coef;
+  const int32_t* status;
+  const int32_t* list;
+  const int32_t* count;
+  Pair<R>* kt;
+  double2* signl;
+};
+
+// One wave per (run, atom), four per workgroup: lane 16 s + k adds value k of segment s
+// (cell shift w = s - 1) over the key's chunks in chunk order; then the Bloch phases, K
+// and the nonlocal part of sigma exactly as at the end of k_bra_mfma.
+template <typename R, typename C>
+__global__ void __launch_bounds__(256) k_bra_fin(BraFinArgs<R, C> a) {
+  __shared__ C gs[4][3][16];
+  __shared__ cplx<C> cs[4][2][4];
+  const int nsl = (a.list != nullptr) ? *a.count : a.nruns;
+  const int nl = min(a.nlogical, nsl * ((a.n_atoms + 3) / 4));
+  const int lb = remap_active(blockIdx.x, nl);
+  if (lb < 0) return;
+  const int agr = (a.n_atoms + 3) / 4;
+  const int slot = lb / agr;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int atom = (lb - slot * agr) * 4 + wv;
+  int run = (a.list != nullptr) ? a.list[slot] : slot;
+  if (a.status != nullptr && a.status[run] != a.need_status) run = -1;
+  const bool ok = run >= 0 && atom < a.n_atoms;
+  if (ok && lane < 48) {
+    const int sg = lane >> 4, k = lane & 15;
+    const int key = 3 * atom + sg;
+    C sum = 0;
+    const C* pr = a.part + (int64_t)run * a.nslots * 16 + k;
+    const int t0 = a.key_off[key], t1 = a.key_off[key + 1];
+    // eight slots at a time: their indices, then their values, each batch of loads in flight
+    // together; the additions stay in chunk order
+    for (int t = t0; t < t1; t += 8) {
+      int g[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) g[q] = a.key_slot[min(t + q, t1 - 1)];
+      C x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[q] = pr[(int64_t)g[q] * 16];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (t + q < t1) sum += x[q];
+    }
+    gs[wv][sg][k] = sum;
+  }
+  __syncthreads();
+  if (ok && lane < 8) {
+    // c[half][i] = sum_s z^w c_s: w = -1 -> 1/z (primal) or conj z (dual), +1 -> z or 1/conj z
+    const int h2 = lane >> 2, i = lane & 3;
+    const RunCoef& cf = a.coef[run];
+    cplx<C> acc = mkc<C>(0, 0);
+    for (int sg = 0; sg < 3; ++sg) {
+      const cplx<C> c = mkc<C>(gs[wv][sg][4 * i + 2 * h2], gs[wv][sg][4 * i + 2 * h2 + 1]);
+      cplx<C> t = c;
+      if (sg != 1) t = cmul<C>(ccast<C, double>(cf.c[3 * h2 + (sg == 0 ? 2 : 1)]), c);
+      acc = cadd<C>(acc, t);
+    }
+    cs[wv][h2][i] = acc;
+  }
+  __syncthreads();
+  if (ok && lane < 24) {
+    const int h2 = lane & 1, i = (lane >> 1) & 3, sw = lane >> 3;
+    const RunCoef& cf = a.coef[run];
+    // K[w][i] = h z^-w c: w = -1 -> cp, 0 -> c0, +1 -> cm
+    const cplx<C> f = ccast<C, double>(cf.c[3 * h2 + (sw == 0 ? 1 : sw == 1 ? 0 : 2)]);
+    const cplx<C> k = cscale<C>(cmul<C>(f, cs[wv][h2][i]), (C)a.coeff[4 * atom + i]);
+    cplx<R>* dst = reinterpret_cast<cplx<R>*>(&a.kt[((int64_t)run * a.n_atoms + atom) * 12 + sw * 4 + i]);
+    dst[h2] = ccast<R, C>(k);
+  }
+  if (ok && a.signl != nullptr && lane == 32) {
+    double2 sg = make_double2(0.0, 0.0);
+    for (int i = 0; i < 4; ++i) {
+      const cplx<C> t = cscale<C>(cmulc<C>(cs[wv][1][i], cs[wv][0][i]), (C)a.coeff[4 * atom + i]);
+      sg.x += (double)t.x;
+      sg.y += (double)t.y;
+    }
+    a.signl[(int64_t)run * a.n_atoms + atom] = sg;
+  }
+}
+
+size_t bra_tile_part_bytes(const cbs_system* s, int32_t nruns) {
+  const int32_t ns = std::max(s->proj.bt[0].nslots, s->proj.bt[1].nslots);
+  return (size_t)std::max(nruns, 0) * (size_t)ns * 16 * sizeof(double);
+}
+
+template <typename R, typename C, int RG>
+static void launch_tile_tp(int tp, int grid, hipStream_t st, const BraTileArgs<R, C>& t) {
+  if (tp == 256)
+    hipLaunchKernelGGL((k_bra_tile<R, C, RG, 256>), dim3(grid), dim3(BT_MAXP * RG), 0, st, t);
+  else
+    hipLaunchKernelGGL((k_bra_tile<R, C, RG, 512>), dim3(grid), dim3(BT_MAXP * RG), 0, st, t);
+}
+
+template <typename R, typename C>
+static int32_t launch_bra_tile(const cbs_system* s, const ChunkTables& d, int rg, int32_t nruns, const void* v,
+                               const RunCoef* coef, const int32_t* status, int32_t need_status, void* kt,
+                               double2* signl, hipStream_t st, const int32_t* list, const int32_t* count,
+                               void* part) {
+  const Projector& pr = s->proj;
+  if (d.tp != 256 && d.tp != 512) {
+    set_error("chunked bra: chunk length %d unsupported", d.tp);
+    return CBS_EINVAL;
+  }
+  BraTileArgs<R, C> t;
+  t.nruns = nruns;
+  t.nchunks = d.nchunks;
+  t.nslots = d.nslots;
+  t.need_status = need_status;
+  t.nlogical = ((nruns + rg - 1) / rg) * d.nchunks;
+  t.N = s->N;
+  t.piece_off = d.piece_off;
+  t.piece_beg = d.piece_beg;
+  t.piece_meta = d.piece_meta;
+  t.slot_off = d.slot_off;
+  t.slot_piece = d.slot_piece;
+  t.ent_pt = d.ent_pt;
+  t.ent_u = std::is_same<R, double>::value ? (const R*)d.u64 : (const R*)d.u32;
+  t.v = (const Pair<R>*)v;
+  t.status = status;
+  t.list = list;
+  t.count = count;
+  t.part = (C*)part;
+  const int grid = (t.nlogical + 7) / 8 * 8;
+  if (rg == 4)
+    launch_tile_tp<R, C, 4>(d.tp, grid, st, t);
+  else if (rg == 8)
+    launch_tile_tp<R, C, 8>(d.tp, grid, st, t);
+  else {
+    set_error("chunked bra: %d runs per workgroup unsupported", rg);
+    return CBS_EINVAL;
+  }
+  CBS_HIP(hipGetLastError());
+  BraFinArgs<R, C> f;
+  f.nruns = nruns;
+  f.n_atoms = pr.n_atoms;
+  f.nslots = d.nslots;
+  f.need_status = need_status;
+  f.nlogical = nruns * ((pr.n_atoms + 3) / 4);
+  f.key_off = d.key_off;
+  f.key_slot = d.key_slot;
+  f.part = (const C*)part;
+  f.coeff = std::is_same<R, double>::value ? (const R*)pr.coeff64 : (const R*)pr.coeff32;
+  f.coef = coef;
+  f.status = status;
+  f.list = list;
+  f.count = count;
+  f.kt = (Pair<R>*)kt;
+  f.signl = signl;
+  const int fgrid = (f.nlogical + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_bra_fin<R, C>), dim3(fgrid), dim3(256), 0, st, f);
+  CBS_HIP(hipGetLastError());
+  return CBS_OK;
+}
+
 static bool bra_plain() {
   const char* e = getenv("CBS_NO_MFMA");
   return e && e[0] == '1';
@@ -312,9 +641,25 @@ template <typename R>
 int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunCoef* coef,
                    const int32_t* status, int32_t need_status, void* kt, double2* signl,
                    hipStream_t st, bool phased, const int32_t* list, const int32_t* count,
-                   bool short_list) {
+                   bool short_list, void* tile_part) {
   const Projector& pr = s->proj;
   if (pr.n_atoms == 0 || nruns <= 0) return CBS_OK;
+  const int pi = std::is_same<R, float>::value ? 1 : 0;
+  if (tile_part != nullptr && phased && !short_list && !bra_plain() && s->bra_tile[pi] > 0 &&
+      pr.bt[s->bra_tp[pi]].nslots > 0) {
+    const ChunkTables& d = pr.bt[s->bra_tp[pi]];
+    if ((list == nullptr) != (count == nullptr)) {
+      set_error("launch_bra: a run list needs its count");
+      return CBS_EINVAL;
+    }
+    if constexpr (std::is_same<R, float>::value) {
+      if (lo_arith_fp32())
+        return launch_bra_tile<R, float>(s, d, s->bra_tile[pi], nruns, v, coef, status, need_status, kt, signl,
+                                         st, list, count, tile_part);
+    }
+    return launch_bra_tile<R, double>(s, d, s->bra_tile[pi], nruns, v, coef, status, need_status, kt, signl,
+                                      st, list, count, tile_part);
+  }
   BraArgs<R> a;
   a.nruns = nruns;
   a.n_atoms = pr.n_atoms;
@@ -333,7 +678,7 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
   a.list = list;   // runs: the list entries, or all runs (both filtered by status if given)
   a.count = count;
   const char* bm = getenv("CBS_BRA_MAP");
-  a.spread = !(bm && bm[0] == 'x');
+  a.spread = bm ? !(bm[0] == 'x') : (s->bra_spread[pi] != 0);
   if ((list == nullptr) != (count == nullptr)) {
     set_error("launch_bra: a run list needs its count");
     return CBS_EINVAL;
@@ -346,8 +691,12 @@ int32_t launch_bra(const cbs_system* s, int32_t nruns, const void* v, const RunC
       hipLaunchKernelGGL((k_bra_mfma<R, float, 16>), dim3(grid), dim3(1024), 0, st, a);
     else if (short_list)
       hipLaunchKernelGGL((k_bra_mfma<R, double, 16>), dim3(grid), dim3(1024), 0, st, a);
+    else if (f32 && s->bra_nw[pi] == 8)
+      hipLaunchKernelGGL((k_bra_mfma<R, float, 8>), dim3(grid), dim3(512), 0, st, a);
     else if (f32)
       hipLaunchKernelGGL((k_bra_mfma<R, float, 4>), dim3(grid), dim3(256), 0, st, a);
+    else if (s->bra_nw[pi] == 8)
+      hipLaunchKernelGGL((k_bra_mfma<R, double, 8>), dim3(grid), dim3(512), 0, st, a);
     else
       hipLaunchKernelGGL((k_bra_mfma<R, double, 4>), dim3(grid), dim3(256), 0, st, a);
   } else {
@@ -555,7 +904,7 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
 }
 
 int32_t update_chunks(const cbs_system* s) {
-  const int64_t per = 256 * 8;
+  const int64_t per = std::max<int64_t>(s->upd_pts, 256);
   return (int32_t)((s->N + per - 1) / per);
 }
 
@@ -678,7 +1027,7 @@ int32_t launch_from_pairs(int64_t N, int32_t nvec, const void* pairs, void* y, h
 #define INST(R)                                                                                   \
   template int32_t launch_bra<R>(const cbs_system*, int32_t, const void*, const RunCoef*,         \
                                  const int32_t*, int32_t, void*, double2*, hipStream_t, bool,     \
-                                 const int32_t*, const int32_t*, bool);                           \
+                                 const int32_t*, const int32_t*, bool, void*);                    \
   template int32_t launch_update<R>(const cbs_system*, int32_t, void*, const void*, const void*,  \
                                     const double2*, const int32_t*, int32_t, double*, int32_t,    \
                                     hipStream_t, const int32_t*, const int32_t*);                 \

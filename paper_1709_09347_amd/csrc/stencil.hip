@@ -16,6 +16,7 @@
 //  * blocks are renumbered so that consecutive tiles of a run land on one XCD, where
 //    they share the halo rows in that XCD's L2.
 #include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 #include "cbs_internal.hpp"
@@ -491,18 +492,164 @@ static int32_t tune_one(cbs_system* s, hipStream_t st, int32_t* best_ty, std::st
   return CBS_OK;
 }
 
+// Times the full-batch projector bra for 4 or 8 waves per (atom, 16 runs) and for the two
+// block orders (consecutive workgroups on one XCD or spread over the XCDs), and (complex128
+// only) the residual update for 1024, 2048 and 4096 points per chunk; keeps the fastest of
+// each.  Same scratch batch as the stencil tiles.
+template <typename R>
+static int32_t tune_nonlocal(cbs_system* s, hipStream_t st, bool tune_update, std::string& log) {
+  const int pi = std::is_same<R, float>::value ? 1 : 0;
+  const size_t per_run = (size_t)s->N * sizeof(Pair<R>);
+  const int nr = (int)std::min<size_t>(256, std::max<size_t>(8, ((size_t)2 << 30) / (5 * per_run)));
+  const int na = s->proj.n_atoms;
+  Pair<R>* buf = nullptr;
+  Pair<R>* kt = nullptr;
+  RunCoef* coef = nullptr;
+  double2* dsc = nullptr;
+  int32_t* status = nullptr;
+  double* part = nullptr;
+  CBS_TRY(ws_get(s->ws, "tune.buf", (size_t)5 * nr * s->N, &buf));
+  CBS_TRY(ws_get(s->ws, "tune.kt", (size_t)nr * na * 12, &kt));
+  CBS_TRY(ws_get(s->ws, "tune.coef", (size_t)nr, &coef));
+  CBS_TRY(ws_get(s->ws, "tune.dsc", (size_t)nr * (na + 1), &dsc));
+  CBS_TRY(ws_get(s->ws, "tune.status", (size_t)nr, &status));
+  CBS_TRY(ws_get(s->ws, "tune.part", (size_t)nr * ((s->N + 1023) / 1024) * 4, &part));
+  CBS_HIP(hipMemsetAsync(kt, 0, (size_t)nr * na * 12 * sizeof(Pair<R>), st));
+  CBS_HIP(hipMemsetAsync(dsc, 0, (size_t)nr * (na + 1) * sizeof(double2), st));
+  hipEvent_t e0, e1;
+  CBS_HIP(hipEventCreate(&e0));
+  CBS_HIP(hipEventCreate(&e1));
+  struct EvG {
+    hipEvent_t a, b;
+    ~EvG() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evg{e0, e1};
+  const char* tag = sizeof(R) == 8 ? "c128" : "c64";
+  float best = 1e30f;
+  int bnw = 4, bsp = 1;
+  for (int nw : {4, 8})
+    for (int sp : {1, 0}) {
+      s->bra_nw[pi] = nw;
+      s->bra_spread[pi] = sp;
+      CBS_TRY(launch_bra<R>(s, nr, buf, coef, status, 0, kt, dsc + nr, st, true));
+      CBS_HIP(hipEventRecord(e0, st));
+      for (int k = 0; k < 3; ++k) CBS_TRY(launch_bra<R>(s, nr, buf, coef, status, 0, kt, dsc + nr, st, true));
+      CBS_HIP(hipEventRecord(e1, st));
+      CBS_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      CBS_HIP(hipEventElapsedTime(&ms, e0, e1));
+      char line[96];
+      snprintf(line, sizeof(line), "%s bra nw=%d spread=%d %.4f ms; ", tag, nw, sp, ms / 3);
+      log += line;
+      if (ms < best) {
+        best = ms;
+        bnw = nw;
+        bsp = sp;
+      }
+    }
+  s->bra_nw[pi] = bnw;
+  s->bra_spread[pi] = bsp;
+  // the chunked bra with 4, 8 (and in complex64 16) runs per workgroup, for each chunk length
+  int btile = 0, btp = 1;
+  const size_t bpart_bytes = bra_tile_part_bytes(s, nr);
+  if (bpart_bytes > 0) {
+    unsigned char* bpart = nullptr;
+    CBS_TRY(ws_get(s->ws, "tune.bpart", bpart_bytes, &bpart));
+    for (int ti = 0; ti < 2; ++ti) {
+      if (s->proj.bt[ti].nslots == 0) continue;
+      s->bra_tp[pi] = ti;
+      for (int rg : {4, 8}) {
+        s->bra_tile[pi] = rg;
+        CBS_TRY(launch_bra<R>(s, nr, buf, coef, status, 0, kt, dsc + nr, st, true, nullptr, nullptr, false, bpart));
+        CBS_HIP(hipEventRecord(e0, st));
+        for (int k = 0; k < 3; ++k)
+          CBS_TRY(launch_bra<R>(s, nr, buf, coef, status, 0, kt, dsc + nr, st, true, nullptr, nullptr, false, bpart));
+        CBS_HIP(hipEventRecord(e1, st));
+        CBS_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        CBS_HIP(hipEventElapsedTime(&ms, e0, e1));
+        char line[96];
+        snprintf(line, sizeof(line), "%s chunked bra %d runs x %d points %.4f ms; ", tag, rg, BT_TPS[ti], ms / 3);
+        log += line;
+        if (ms < best) {
+          best = ms;
+          btile = rg;
+          btp = ti;
+        }
+      }
+    }
+  }
+  s->bra_tile[pi] = btile;
+  s->bra_tp[pi] = btp;
+  if (tune_update) {
+    best = 1e30f;
+    int bpts = 2048;
+    for (int pts : {1024, 2048, 4096}) {
+      s->upd_pts = pts;
+      const int nch = update_chunks(s);
+      CBS_TRY(launch_update<R>(s, nr, buf, buf + (size_t)nr * s->N, kt, dsc, status, 0, part, nch, st));
+      CBS_HIP(hipEventRecord(e0, st));
+      for (int k = 0; k < 3; ++k)
+        CBS_TRY(launch_update<R>(s, nr, buf, buf + (size_t)nr * s->N, kt, dsc, status, 0, part, nch, st));
+      CBS_HIP(hipEventRecord(e1, st));
+      CBS_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      CBS_HIP(hipEventElapsedTime(&ms, e0, e1));
+      char line[96];
+      snprintf(line, sizeof(line), "%s update %d pts/chunk %.4f ms; ", tag, pts, ms / 3);
+      log += line;
+      if (ms < best) {
+        best = ms;
+        bpts = pts;
+      }
+    }
+    s->upd_pts = bpts;
+  }
+  return CBS_OK;
+}
+
+// CBS_BRA_TILE=<runs>[:<points>] fixes the full-batch bra after tuning: runs 0 = per atom,
+// 4 or 8 = chunked with that many runs per workgroup, on chunks of 256 or 512 points
+// (default 512).
+static int32_t bra_override(cbs_system* s) {
+  const char* e = getenv("CBS_BRA_TILE");
+  if (e == nullptr || e[0] == 0) return CBS_OK;
+  const int rg = atoi(e);
+  const char* colon = strchr(e, ':');
+  const int tp = colon ? atoi(colon + 1) : 512;
+  if ((rg != 0 && rg != 4 && rg != 8) || (tp != 256 && tp != 512)) {
+    set_error("CBS_BRA_TILE=%s: expected 0, 4 or 8 runs, optionally :256 or :512 points", e);
+    return CBS_EINVAL;
+  }
+  const int ti = tp == 256 ? 0 : 1;
+  if (rg > 0 && s->proj.bt[ti].nslots == 0) return CBS_OK;   // no chunked tables for this cell
+  s->bra_tile[0] = s->bra_tile[1] = rg;
+  s->bra_tp[0] = s->bra_tp[1] = ti;
+  return CBS_OK;
+}
+
 int32_t autotune_tiles(cbs_system* s, hipStream_t st) {
   if (s->tuned) return CBS_OK;
   const char* e = getenv("CBS_AUTOTUNE");
   if (e && e[0] == '0') {
+    CBS_TRY(bra_override(s));
     s->tuned = 1;
     return CBS_OK;
   }
   std::string log;
   CBS_TRY(tune_one<double>(s, st, &s->tile_y[0], log));
   CBS_TRY(tune_one<float>(s, st, &s->tile_y[1], log));
+  if (s->proj.n_atoms > 0) {
+    CBS_TRY(tune_nonlocal<double>(s, st, true, log));
+    CBS_TRY(tune_nonlocal<float>(s, st, false, log));
+  }
   CBS_HIP(hipStreamSynchronize(st));
-  for (const char* n : {"tune.buf", "tune.coef", "tune.sc", "tune.status", "tune.sig"}) s->ws.drop(n);
+  for (const char* n : {"tune.buf", "tune.coef", "tune.sc", "tune.status", "tune.sig", "tune.kt", "tune.dsc",
+                        "tune.part", "tune.bpart"})
+    s->ws.drop(n);
+  CBS_TRY(bra_override(s));
   s->tune_log = log;
   s->tuned = 1;
   return CBS_OK;

@@ -182,6 +182,29 @@ static int32_t build_projectors(cbs_system* s, const cbs_proj* pr) {
   CBS_TRY(upload(grp_mask, &P.grp_mask));
   CBS_TRY(upload(grp_u, &P.grp_u64));
   CBS_TRY(upload(grp_u32, &P.grp_u32));
+  // chunked bra tables for each chunk length; a length whose chunks hold more keys than the
+  // pieces allowed is left out (the per-atom bra remains)
+  for (int ti = 0; ti < 2; ++ti) {
+    BraTileTables bt;
+    if (!build_bra_tile_tables(s->N, A, seg, idx, u64, BT_TPS[ti], BT_MAXP, bt).empty() || bt.key_slot.empty())
+      continue;
+    ChunkTables& d = P.bt[ti];
+    std::vector<float> btu32(bt.ent_u.begin(), bt.ent_u.end());
+    CBS_TRY(upload(bt.piece_off, &d.piece_off));
+    CBS_TRY(upload(bt.piece_beg, &d.piece_beg));
+    CBS_TRY(upload(bt.piece_meta, &d.piece_meta));
+    CBS_TRY(upload(bt.slot_off, &d.slot_off));
+    CBS_TRY(upload(bt.slot_piece, &d.slot_piece));
+    CBS_TRY(upload(bt.ent_pt, &d.ent_pt));
+    CBS_TRY(upload(bt.ent_u, &d.u64));
+    CBS_TRY(upload(btu32, &d.u32));
+    CBS_TRY(upload(bt.key_off, &d.key_off));
+    CBS_TRY(upload(bt.key_slot, &d.key_slot));
+    d.tp = BT_TPS[ti];
+    d.nchunks = bt.nchunks;
+    d.nslots = (int32_t)bt.key_slot.size();
+    d.pl = bt.pl;
+  }
   std::vector<float> u32(u64.begin(), u64.end()), ptu32(pt_u.begin(), pt_u.end()),
       cf32(cf.begin(), cf.end());
   P.n_atoms = A;
@@ -221,6 +244,18 @@ static void free_system(cbs_system* s) {
   f(P.grp_mask);
   f(P.grp_u64);
   f(P.grp_u32);
+  for (ChunkTables& d : P.bt) {
+    f(d.piece_off);
+    f(d.piece_beg);
+    f(d.piece_meta);
+    f(d.slot_off);
+    f(d.slot_piece);
+    f(d.ent_pt);
+    f(d.u64);
+    f(d.u32);
+    f(d.key_off);
+    f(d.key_slot);
+  }
   f(s->last.vecs);
   s->ws.release();
 }
