@@ -100,7 +100,8 @@ typedef struct {
   int32_t n_q;          /* trapezoid nodes per circle (N_int) */
   int32_t n_rhs;        /* right-hand sides L (N_rh) */
   int32_t n_mom;        /* moments M (N_mm); Hankel size L*M <= 256; 2*M <= n_q */
-  double delta;         /* SVD rank threshold, relative to the largest singular value */
+  double delta;         /* SVD rank threshold, relative to the largest singular value (raised to
+                           100x the largest relative residual of the solves when that is higher) */
   double tol;           /* per-column relative residual of every solve (primal and dual) */
   int32_t max_iter;     /* BiCG iteration cap (per inner solve) */
   int32_t precision;    /* CBS_FP64, or CBS_MIXED: complex128 BiCG until a run's residual is

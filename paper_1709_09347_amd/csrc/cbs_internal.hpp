@@ -208,14 +208,14 @@ struct ChunkTables {
   int32_t tp = 0, nchunks = 0, nslots = 0, pl = 0;
   int32_t* piece_off = nullptr;   // [nchunks+1]
   int32_t* piece_beg = nullptr;   // [npieces]
-  int32_t* piece_meta = nullptr;  // [npieces] (local slot << 16) | entry count
+  int32_t* piece_meta = nullptr;  // [npieces] (local slot << 16) | entry count (a multiple of BT_EB)
   int32_t* slot_off = nullptr;    // [nchunks+1]
   int32_t* slot_piece = nullptr;  // [nslots+1]
-  int32_t* ent_pt = nullptr;      // [nnz] point within the chunk
-  double* u64 = nullptr;          // [nnz][4]
+  int32_t* ent_pt = nullptr;      // [entries] point within the chunk (padding: 0)
+  double* u64 = nullptr;          // [entries][4] (padding: 0)
   float* u32 = nullptr;
-  int32_t* key_off = nullptr;     // [3*n_atoms+1]
-  int32_t* key_slot = nullptr;    // [nslots]
+  int32_t* key_off = nullptr;     // [3*n_atoms+1] slots of key k: [key_off[k], key_off[k+1]) in key order
+  int32_t* slot_pos = nullptr;    // [nslots] position of slot g in key order (chunk order within a key)
 };
 
 struct Projector {
@@ -253,6 +253,7 @@ struct Projector {
 constexpr int KG = 64;        // points per ket group (one wavefront)
 constexpr int BT_TPS[2] = {256, 512};   // points per chunk of the chunked bra
 constexpr int BT_MAXP = 128;             // pieces per chunk of the chunked bra
+constexpr int BT_EB = 4;                 // entries per batch of the chunked bra (pieces padded to it)
 
 struct LastSolve {
   int32_t n = 0;

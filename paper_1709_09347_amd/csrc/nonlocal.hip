@@ -323,13 +323,14 @@ struct BraTileArgs {
   const int32_t* piece_meta;
   const int32_t* slot_off;
   const int32_t* slot_piece;
+  const int32_t* slot_pos;
   const int32_t* ent_pt;
   const R* ent_u;
   const Pair<R>* v;
   const int32_t* status;
   const int32_t* list;
   const int32_t* count;
-  C* part;   // [run][slot][16]: u_i times (primal re, primal im, dual re, dual im), i major
+  C* part;   // [run][slot in key order][16]: u_i times (primal re, primal im, dual re, dual im), i major
 };
 
 // BT_MAXP x RG threads: thread t takes piece t / RG of the chunk (at most BT_MAXP) for run
@@ -346,7 +347,7 @@ __global__ void __launch_bounds__(BT_MAXP * RG, 4) k_bra_tile(BraTileArgs<R, C> 
   constexpr int LDSB = VB > SB ? VB : SB;
   static_assert(LDSB <= 160 * 1024, "staging exceeds LDS");
   constexpr int NT = BT_MAXP * RG;
-  constexpr int EB = 4;   // entries whose table loads are issued together
+  constexpr int EB = BT_EB;   // entries whose table loads are issued together (pieces are padded to it)
   using U4 = typename vec4<R>::T;
   __shared__ __attribute__((aligned(16))) unsigned char lds[LDSB];
   __shared__ int srun[RG];
@@ -414,35 +415,23 @@ __global__ void __launch_bounds__(BT_MAXP * RG, 4) k_bra_tile(BraTileArgs<R, C> 
 #pragma unroll
   for (int k = 0; k < 16; ++k) acc[k] = 0;
   if (work) {
-    int pts[EB];
-    U4 us[EB];
-#pragma unroll
-    for (int q = 0; q < EB; ++q) {
-      const int e = min(beg + q, end - 1);
-      pts[q] = a.ent_pt[e];
-      us[q] = ut[e];
-    }
-    for (int e0 = beg;;) {
+    for (int e0 = beg; e0 < end; e0 += EB) {
+      int pts[EB];
+      U4 us[EB];
 #pragma unroll
       for (int q = 0; q < EB; ++q) {
-        // entries past the piece (their index clamped to its last entry) add nothing
+        pts[q] = a.ent_pt[e0 + q];
+        us[q] = ut[e0 + q];
+      }
+#pragma unroll
+      for (int q = 0; q < EB; ++q) {
         const Pair<R> x = vj[pts[q]];
-        const C w = (e0 + q < end) ? (C)1 : (C)0;
-        const C u4[4] = {w * (C)us[q].x, w * (C)us[q].y, w * (C)us[q].z, w * (C)us[q].w};
+        const C u4[4] = {(C)us[q].x, (C)us[q].y, (C)us[q].z, (C)us[q].w};
         const C xs[4] = {(C)x.a.x, (C)x.a.y, (C)x.b.x, (C)x.b.y};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int k = 0; k < 4; ++k) acc[4 * i + k] += u4[i] * xs[k];
-      }
-      e0 += EB;
-      if (e0 >= end) break;
-      // the next batch, indices clamped to the piece
-#pragma unroll
-      for (int q = 0; q < EB; ++q) {
-        const int e = min(e0 + q, end - 1);
-        pts[q] = a.ent_pt[e];
-        us[q] = ut[e];
       }
     }
   }
@@ -465,7 +454,7 @@ __global__ void __launch_bounds__(BT_MAXP * RG, 4) k_bra_tile(BraTileArgs<R, C> 
     const int q0 = a.slot_piece[g] - pb, q1 = a.slot_piece[g + 1] - pb;
     C sum = 0;
     for (int q = q0; q < q1; ++q) sum += psum[(q * RG + jj) * 16 + k];
-    a.part[((int64_t)rr * a.nslots + g) * 16 + k] = sum;
+    a.part[((int64_t)rr * a.nslots + a.slot_pos[g]) * 16 + k] = sum;
   }
 }
 
@@ -473,7 +462,6 @@ template <typename R, typename C>
 struct BraFinArgs {
   int32_t nruns, n_atoms, nslots, need_status, nlogical;
   const int32_t* key_off;
-  const int32_t* key_slot;
   const C* part;
   const R* coeff;
   const RunCoef* coef;
@@ -508,15 +496,12 @@ __global__ void __launch_bounds__(256) k_bra_fin(BraFinArgs<R, C> a) {
     C sum = 0;
     const C* pr = a.part + (int64_t)run * a.nslots * 16 + k;
     const int t0 = a.key_off[key], t1 = a.key_off[key + 1];
-    // eight slots at a time: their indices, then their values, each batch of loads in flight
-    // together; the additions stay in chunk order
+    // the key's chunk sums are contiguous; eight at a time, loads in flight together, the
+    // additions in chunk order
     for (int t = t0; t < t1; t += 8) {
-      int g[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) g[q] = a.key_slot[min(t + q, t1 - 1)];
       C x[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) x[q] = pr[(int64_t)g[q] * 16];
+      for (int q = 0; q < 8; ++q) x[q] = pr[(int64_t)min(t + q, t1 - 1) * 16];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         if (t + q < t1) sum += x[q];
@@ -593,6 +578,7 @@ static int32_t launch_bra_tile(const cbs_system* s, const ChunkTables& d, int rg
   t.piece_meta = d.piece_meta;
   t.slot_off = d.slot_off;
   t.slot_piece = d.slot_piece;
+  t.slot_pos = d.slot_pos;
   t.ent_pt = d.ent_pt;
   t.ent_u = std::is_same<R, double>::value ? (const R*)d.u64 : (const R*)d.u32;
   t.v = (const Pair<R>*)v;
@@ -617,7 +603,6 @@ static int32_t launch_bra_tile(const cbs_system* s, const ChunkTables& d, int rg
   f.need_status = need_status;
   f.nlogical = nruns * ((pr.n_atoms + 3) / 4);
   f.key_off = d.key_off;
-  f.key_slot = d.key_slot;
   f.part = (const C*)part;
   f.coeff = std::is_same<R, double>::value ? (const R*)pr.coeff64 : (const R*)pr.coeff32;
   f.coef = coef;

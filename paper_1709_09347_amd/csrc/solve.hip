@@ -278,11 +278,21 @@ static void moment_weights(const cbs_params* prm, int nq, int nk, std::vector<c6
   }
 }
 
-int32_t extract_S(cbs_system* s, double E, const cbs_params* prm, const c64* V, const c64* S, hipStream_t st,
-                  Extracted& out, double* t_mom_ms, std::chrono::steady_clock::time_point t0);
+int32_t extract_S(cbs_system* s, double E, const cbs_params* prm, double noise, const c64* V, const c64* S,
+                  hipStream_t st, Extracted& out, double* t_mom_ms, std::chrono::steady_clock::time_point t0);
 
-// Steps 2-5 for one system / energy; Y = node solutions (pairs, run = j*L + l).
-int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, const Pair<double>* Y,
+// The largest primal relative residual of the runs [r0, r1) (relres: [run][primal, dual]),
+// finite values only: the noise level of the moments built from those solutions.
+static double solve_noise(const std::vector<double>& relres, int64_t r0, int64_t r1) {
+  double m = 0;
+  for (int64_t r = r0; r < r1; ++r)
+    if (std::isfinite(relres[2 * r])) m = std::max(m, relres[2 * r]);
+  return m;
+}
+
+// Steps 2-5 for one system / energy; Y = node solutions (pairs, run = j*L + l); noise: the
+// largest relative residual of those solutions.
+int32_t extract(cbs_system* s, double E, const cbs_params* prm, double noise, const c64* V, const Pair<double>* Y,
                 int32_t nq_solved, hipStream_t st, Extracted& out, double* t_mom_ms) {
   const int L = prm->n_rhs, M = prm->n_mom, nq = nq_solved, nk = 2 * M;
   const int32_t conj = nq_solved != prm->n_q;
@@ -302,12 +312,12 @@ int32_t extract(cbs_system* s, double E, const cbs_params* prm, const c64* V, co
                        std::min(MOM_CHUNK, nk - k0), Y, (const c64*)dca, (const c64*)dcb, S);
     CBS_HIP(hipGetLastError());
   }
-  return extract_S(s, E, prm, V, S, st, out, t_mom_ms, t0);
+  return extract_S(s, E, prm, noise, V, S, st, out, t_mom_ms, t0);
 }
 
 // Steps 2 (mu_k = V^H S_k) to 5 from the moments S [2M][L][N] of one system / energy.
-int32_t extract_S(cbs_system* s, double E, const cbs_params* prm, const c64* V, const c64* S, hipStream_t st,
-                  Extracted& out, double* t_mom_ms, std::chrono::steady_clock::time_point t0) {
+int32_t extract_S(cbs_system* s, double E, const cbs_params* prm, double noise, const c64* V, const c64* S,
+                  hipStream_t st, Extracted& out, double* t_mom_ms, std::chrono::steady_clock::time_point t0) {
   const int L = prm->n_rhs, M = prm->n_mom, nk = 2 * M, n = L * M;
   const int64_t N = s->N;
   Workspace& ws = s->ws;
@@ -347,212 +357,245 @@ int32_t extract_S(cbs_system* s, double E, const cbs_params* prm, const c64* V, 
     set_error("non-finite singular values of the Hankel matrix (a linear solve diverged)");
     return CBS_ENONFINITE;
   }
-  int m = 0;
-  for (int i = 0; i < n; ++i)
-    if (hsig[i] > prm->delta * hsig[0]) ++m;
-  out.rank = m;
+  // rank: singular values above delta sigma_1 and above the noise floor of the moments,
+  // the solves' largest residual relative to sigma_1: directions below it carry no
+  // information, and in the Rayleigh-Ritz basis they let spurious pairs mix with true ones.
+  // Where the floor is ambiguous (between 10x and 100x that residual) both ranks are tried and
+  // the one giving more eigenpairs, then the smaller largest residual, is kept.
+  auto rank_above = [&](double rel) {
+    const double thr = std::max(prm->delta, std::isfinite(noise) ? rel * noise : 0.0);
+    int r = 0;
+    for (int i = 0; i < n; ++i)
+      if (hsig[i] > thr * hsig[0]) ++r;
+    return r;
+  };
+  const int m_hi = rank_above(100.0), m_lo = rank_above(10.0);
   out.sig1 = hsig[0];
-  out.sig_ratio = (m > 0 && hsig[0] > 0) ? hsig[m - 1] / hsig[0] : 0.0;
   out.lam.clear();
   out.res.clear();
-  if (m == 0 || !(hsig[0] > 0)) return CBS_OK;
-
-  // --- reduced Hankel problem
-  c64 *Up = nullptr, *Wp = nullptr, *TW = nullptr, *Bred = nullptr, *tau = nullptr, *phi = nullptr;
-  CBS_TRY(ws_get(ws, "hk.Up", (size_t)n * m, &Up));
-  CBS_TRY(ws_get(ws, "hk.Wp", (size_t)n * m, &Wp));
-  CBS_TRY(ws_get(ws, "hk.TW", (size_t)n * m, &TW));
-  CBS_TRY(ws_get(ws, "hk.B", (size_t)m * m, &Bred));
-  CBS_TRY(ws_get(ws, "hk.tau", (size_t)2 * n, &tau));
-  CBS_TRY(ws_get(ws, "hk.phi", (size_t)m * m, &phi));
-  hipLaunchKernelGGL(k_gather_cols, dim3(launch_grid((int64_t)n * m)), dim3(256), 0, st, n, m, (const c64*)T, n,
-                     (const int32_t*)perm, Up, n);
-  hipLaunchKernelGGL(k_gather_cols, dim3(launch_grid((int64_t)n * m)), dim3(256), 0, st, n, m, (const c64*)W, n,
-                     (const int32_t*)perm, Wp, n);
-  CBS_HIP(hipGetLastError());
-  CBS_TRY(small_gemm(n, m, n, Tl, n, false, Wp, n, TW, n, nullptr, nullptr, st));
-  // Bred = Up^H TW diag(1/sigma)
-  std::vector<double> inv(m);
-  for (int i = 0; i < m; ++i) inv[i] = 1.0 / hsig[i];
-  double* dinv = nullptr;
-  CBS_TRY(ws_get(ws, "hk.inv", (size_t)m, &dinv));
-  CBS_HIP(hipMemcpyAsync(dinv, inv.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
-  CBS_TRY(small_gemm(m, m, n, Up, n, true, TW, n, Bred, m, dinv, nullptr, st));
-  dump("Bred", Bred, (size_t)m * m * sizeof(c64), st);
-  if (prm->extraction == CBS_HANKEL) {
-    // the reduced Hankel eigenpairs are the result only for the Hankel extraction; the
-    // Rayleigh-Ritz extraction uses the SVD basis alone
-    CBS_TRY(eig(s, m, Bred, m, tau, phi, m, info, st));
-    dump("tau", tau, (size_t)m * sizeof(c64), st);
-    dump("phi", phi, (size_t)m * m * sizeof(c64), st);
+  if (m_lo == 0 || !(hsig[0] > 0)) {
+    out.rank = m_lo;
+    out.sig_ratio = 0.0;
+    return CBS_OK;
   }
+  auto extract_rank = [&](const int m, const char* out_name, Extracted& out) -> int32_t {
+    out.rank = m;
+    out.sig1 = hsig[0];
+    out.sig_ratio = (m > 0 && hsig[0] > 0) ? hsig[m - 1] / hsig[0] : 0.0;
+    out.lam.clear();
+    out.res.clear();
+    if (m == 0) return CBS_OK;
 
-  std::vector<c64> cand;
-  c64* basis = nullptr;   // N x ncand candidate vectors (not normalised)
-  int ncand = 0;
-  const int64_t capv = std::max<int64_t>(2 * m, 1);
-  CBS_TRY(ws_get(ws, "ex.vec", (size_t)capv * N, &basis));
-  if (prm->extraction == CBS_HANKEL) {
-    c64* coef = nullptr;
-    CBS_TRY(ws_get(ws, "hk.coef", (size_t)n * m, &coef));
-    hipLaunchKernelGGL(k_scale_rows_gemm, dim3(launch_grid((int64_t)n * m)), dim3(256), 0, st, n, m, (const c64*)Wp,
-                       (const double*)sig, (const c64*)phi, coef);
+    // --- reduced Hankel problem
+    c64 *Up = nullptr, *Wp = nullptr, *TW = nullptr, *Bred = nullptr, *tau = nullptr, *phi = nullptr;
+    CBS_TRY(ws_get(ws, "hk.Up", (size_t)n * m, &Up));
+    CBS_TRY(ws_get(ws, "hk.Wp", (size_t)n * m, &Wp));
+    CBS_TRY(ws_get(ws, "hk.TW", (size_t)n * m, &TW));
+    CBS_TRY(ws_get(ws, "hk.B", (size_t)m * m, &Bred));
+    CBS_TRY(ws_get(ws, "hk.tau", (size_t)2 * n, &tau));
+    CBS_TRY(ws_get(ws, "hk.phi", (size_t)m * m, &phi));
+    hipLaunchKernelGGL(k_gather_cols, dim3(launch_grid((int64_t)n * m)), dim3(256), 0, st, n, m, (const c64*)T, n,
+                       (const int32_t*)perm, Up, n);
+    hipLaunchKernelGGL(k_gather_cols, dim3(launch_grid((int64_t)n * m)), dim3(256), 0, st, n, m, (const c64*)W, n,
+                       (const int32_t*)perm, Wp, n);
     CBS_HIP(hipGetLastError());
-    CBS_TRY(tall_gemm(N, n, m, S, N, coef, n, basis, N, st));
-    cand.resize(m);
-    CBS_HIP(hipMemcpyAsync(cand.data(), tau, m * sizeof(c64), hipMemcpyDeviceToHost, st));
-    ncand = m;
-  } else {
-    // --- Rayleigh-Ritz on Q = orth(S_{<M} W1): shifted Cholesky QR, then two plain passes
-    c64 *Qa = nullptr, *Qb = nullptr, *G = nullptr, *Ri = nullptr;
-    CBS_TRY(ws_get(ws, "rr.Qa", (size_t)m * N, &Qa));
-    CBS_TRY(ws_get(ws, "rr.Qb", (size_t)m * N, &Qb));
-    CBS_TRY(ws_get(ws, "rr.G", (size_t)m * m, &G));
-    CBS_TRY(ws_get(ws, "rr.Ri", (size_t)m * m, &Ri));
-    CBS_TRY(tall_gemm(N, n, m, S, N, Wp, n, Qa, N, st));
-    for (int pass = 0; pass < 3; ++pass) {
-      CBS_TRY(gram(s, N, m, Qa, N, m, Qa, N, G, m, st));
-      double shift = 0;
-      if (pass == 0) {
-        std::vector<c64> hg((size_t)m * m);
-        CBS_HIP(hipMemcpyAsync(hg.data(), G, hg.size() * sizeof(c64), hipMemcpyDeviceToHost, st));
-        CBS_HIP(hipStreamSynchronize(st));
-        double tr = 0;
-        for (int i = 0; i < m; ++i) tr += hg[(size_t)i * m + i].x;
-        shift = 11.0 * ((double)N * m + (double)m * (m + 1)) * 1.1102230246251565e-16 * tr;
-      }
-      CBS_TRY(chol_inv(m, G, m, shift, Ri, info, st));
-      CBS_TRY(tall_gemm(N, m, m, Qa, N, Ri, m, Qb, N, st));
-      std::swap(Qa, Qb);
+    CBS_TRY(small_gemm(n, m, n, Tl, n, false, Wp, n, TW, n, nullptr, nullptr, st));
+    // Bred = Up^H TW diag(1/sigma)
+    std::vector<double> inv(m);
+    for (int i = 0; i < m; ++i) inv[i] = 1.0 / hsig[i];
+    double* dinv = nullptr;
+    CBS_TRY(ws_get(ws, "hk.inv", (size_t)m, &dinv));
+    CBS_HIP(hipMemcpyAsync(dinv, inv.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
+    CBS_TRY(small_gemm(m, m, n, Up, n, true, TW, n, Bred, m, dinv, nullptr, st));
+    dump("Bred", Bred, (size_t)m * m * sizeof(c64), st);
+    if (prm->extraction == CBS_HANKEL) {
+      // the reduced Hankel eigenpairs are the result only for the Hankel extraction; the
+      // Rayleigh-Ritz extraction uses the SVD basis alone
+      CBS_TRY(eig(s, m, Bred, m, tau, phi, m, info, st));
+      dump("tau", tau, (size_t)m * sizeof(c64), st);
+      dump("phi", phi, (size_t)m * m * sizeof(c64), st);
     }
-    // projected blocks A0 = Q^H (H0-E) Q, A+ = Q^H H+ Q, A- = Q^H H- Q
-    c64 *HQ = nullptr, *A3 = nullptr;
-    CBS_TRY(ws_get(ws, "rr.HQ", (size_t)3 * m * N, &HQ));
-    CBS_TRY(ws_get(ws, "rr.A3", (size_t)3 * m * m, &A3));
-    std::vector<c64> one(m, make_double2(1, 0)), zero(m, make_double2(0, 0));
-    CBS_TRY(apply_parts_dev(s, E, m, one.data(), zero.data(), zero.data(), Qa, HQ, st));
-    CBS_TRY(apply_parts_dev(s, E, m, zero.data(), one.data(), zero.data(), Qa, HQ + (size_t)m * N, st));
-    CBS_TRY(apply_parts_dev(s, E, m, zero.data(), zero.data(), one.data(), Qa, HQ + (size_t)2 * m * N, st));
-    for (int p = 0; p < 3; ++p)
-      CBS_TRY(gram(s, N, m, Qa, N, m, HQ + (size_t)p * m * N, N, A3 + (size_t)p * m * m, m, st));
-    const int n2 = 2 * m;
-    c64 *X = nullptr, *Bl = nullptr, *th = nullptr, *vv = nullptr;
-    CBS_TRY(ws_get(ws, "rr.X", (size_t)n2 * n2, &X));
-    CBS_TRY(ws_get(ws, "rr.B", (size_t)n2 * n2, &Bl));
-    CBS_TRY(ws_get(ws, "rr.th", (size_t)n2, &th));
-    CBS_TRY(ws_get(ws, "rr.vv", (size_t)n2 * n2, &vv));
-    const c64 sft = make_double2(0.83 * cos(0.7654), 0.83 * sin(0.7654));
-    hipLaunchKernelGGL(k_linearize, dim3(launch_grid((int64_t)n2 * n2)), dim3(256), 0, st, m, (const c64*)A3,
-                       (const c64*)(A3 + (size_t)m * m), (const c64*)(A3 + (size_t)2 * m * m), sft, X, Bl);
-    CBS_HIP(hipGetLastError());
-    dump("Q", Qa, (size_t)m * N * sizeof(c64), st);
-    dump("A3", A3, (size_t)3 * m * m * sizeof(c64), st);
-    CBS_TRY(lu_solve(n2, X, n2, Bl, n2, n2, info, st));
-    dump("Minv", Bl, (size_t)n2 * n2 * sizeof(c64), st);
-    CBS_TRY(eig(s, n2, Bl, n2, th, vv, n2, info, st));
-    dump("theta", th, (size_t)n2 * sizeof(c64), st);
-    std::vector<c64> hth(n2);
-    CBS_HIP(hipMemcpyAsync(hth.data(), th, n2 * sizeof(c64), hipMemcpyDeviceToHost, st));
-    CBS_HIP(hipStreamSynchronize(st));
-    double thmax = 0;
-    for (auto& t : hth) thmax = std::max(thmax, sqrt(cabs2<double>(t)));
-    // keep finite eigenvalues inside (a slightly widened) annulus; x = top half of v
-    std::vector<int32_t> keep;
-    const double lmin = prm->lambda_min;
-    for (int i = 0; i < n2; ++i) {
-      if (!(sqrt(cabs2<double>(hth[i])) > 1e-13 * thmax)) continue;
-      const c64 lam = cadd<double>(sft, cdiv<double>(make_double2(1, 0), hth[i]));
-      const double a = sqrt(cabs2<double>(lam));
-      if (a > lmin * (1 - 1e-9) && a < (1 + 1e-9) / lmin) {
-        keep.push_back(i);
-        cand.push_back(lam);
-      }
-    }
-    ncand = (int)keep.size();
-    if (ncand > 0) {
-      int32_t* dkeep = nullptr;
-      c64* Xt = nullptr;
-      CBS_TRY(ws_get(ws, "rr.keep", (size_t)ncand, &dkeep));
-      CBS_TRY(ws_get(ws, "rr.Xt", (size_t)m * ncand, &Xt));
-      CBS_HIP(hipMemcpyAsync(dkeep, keep.data(), ncand * sizeof(int32_t), hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(k_gather_cols, dim3(launch_grid((int64_t)m * ncand)), dim3(256), 0, st, m, ncand,
-                         (const c64*)vv, n2, (const int32_t*)dkeep, Xt, m);
+
+    std::vector<c64> cand;
+    c64* basis = nullptr;   // N x ncand candidate vectors (not normalised)
+    int ncand = 0;
+    const int64_t capv = std::max<int64_t>(2 * m, 1);
+    CBS_TRY(ws_get(ws, "ex.vec", (size_t)capv * N, &basis));
+    if (prm->extraction == CBS_HANKEL) {
+      c64* coef = nullptr;
+      CBS_TRY(ws_get(ws, "hk.coef", (size_t)n * m, &coef));
+      hipLaunchKernelGGL(k_scale_rows_gemm, dim3(launch_grid((int64_t)n * m)), dim3(256), 0, st, n, m, (const c64*)Wp,
+                         (const double*)sig, (const c64*)phi, coef);
       CBS_HIP(hipGetLastError());
-      CBS_TRY(tall_gemm(N, m, ncand, Qa, N, Xt, m, basis, N, st));
+      CBS_TRY(tall_gemm(N, n, m, S, N, coef, n, basis, N, st));
+      cand.resize(m);
+      CBS_HIP(hipMemcpyAsync(cand.data(), tau, m * sizeof(c64), hipMemcpyDeviceToHost, st));
+      ncand = m;
+    } else {
+      // --- Rayleigh-Ritz on Q = orth(S_{<M} W1): shifted Cholesky QR, then two plain passes
+      c64 *Qa = nullptr, *Qb = nullptr, *G = nullptr, *Ri = nullptr;
+      CBS_TRY(ws_get(ws, "rr.Qa", (size_t)m * N, &Qa));
+      CBS_TRY(ws_get(ws, "rr.Qb", (size_t)m * N, &Qb));
+      CBS_TRY(ws_get(ws, "rr.G", (size_t)m * m, &G));
+      CBS_TRY(ws_get(ws, "rr.Ri", (size_t)m * m, &Ri));
+      CBS_TRY(tall_gemm(N, n, m, S, N, Wp, n, Qa, N, st));
+      for (int pass = 0; pass < 3; ++pass) {
+        CBS_TRY(gram(s, N, m, Qa, N, m, Qa, N, G, m, st));
+        double shift = 0;
+        if (pass == 0) {
+          std::vector<c64> hg((size_t)m * m);
+          CBS_HIP(hipMemcpyAsync(hg.data(), G, hg.size() * sizeof(c64), hipMemcpyDeviceToHost, st));
+          CBS_HIP(hipStreamSynchronize(st));
+          double tr = 0;
+          for (int i = 0; i < m; ++i) tr += hg[(size_t)i * m + i].x;
+          shift = 11.0 * ((double)N * m + (double)m * (m + 1)) * 1.1102230246251565e-16 * tr;
+        }
+        CBS_TRY(chol_inv(m, G, m, shift, Ri, info, st));
+        CBS_TRY(tall_gemm(N, m, m, Qa, N, Ri, m, Qb, N, st));
+        std::swap(Qa, Qb);
+      }
+      // projected blocks A0 = Q^H (H0-E) Q, A+ = Q^H H+ Q, A- = Q^H H- Q
+      c64 *HQ = nullptr, *A3 = nullptr;
+      CBS_TRY(ws_get(ws, "rr.HQ", (size_t)3 * m * N, &HQ));
+      CBS_TRY(ws_get(ws, "rr.A3", (size_t)3 * m * m, &A3));
+      std::vector<c64> one(m, make_double2(1, 0)), zero(m, make_double2(0, 0));
+      CBS_TRY(apply_parts_dev(s, E, m, one.data(), zero.data(), zero.data(), Qa, HQ, st));
+      CBS_TRY(apply_parts_dev(s, E, m, zero.data(), one.data(), zero.data(), Qa, HQ + (size_t)m * N, st));
+      CBS_TRY(apply_parts_dev(s, E, m, zero.data(), zero.data(), one.data(), Qa, HQ + (size_t)2 * m * N, st));
+      for (int p = 0; p < 3; ++p)
+        CBS_TRY(gram(s, N, m, Qa, N, m, HQ + (size_t)p * m * N, N, A3 + (size_t)p * m * m, m, st));
+      const int n2 = 2 * m;
+      c64 *X = nullptr, *Bl = nullptr, *th = nullptr, *vv = nullptr;
+      CBS_TRY(ws_get(ws, "rr.X", (size_t)n2 * n2, &X));
+      CBS_TRY(ws_get(ws, "rr.B", (size_t)n2 * n2, &Bl));
+      CBS_TRY(ws_get(ws, "rr.th", (size_t)n2, &th));
+      CBS_TRY(ws_get(ws, "rr.vv", (size_t)n2 * n2, &vv));
+      const c64 sft = make_double2(0.83 * cos(0.7654), 0.83 * sin(0.7654));
+      hipLaunchKernelGGL(k_linearize, dim3(launch_grid((int64_t)n2 * n2)), dim3(256), 0, st, m, (const c64*)A3,
+                         (const c64*)(A3 + (size_t)m * m), (const c64*)(A3 + (size_t)2 * m * m), sft, X, Bl);
+      CBS_HIP(hipGetLastError());
+      dump("Q", Qa, (size_t)m * N * sizeof(c64), st);
+      dump("A3", A3, (size_t)3 * m * m * sizeof(c64), st);
+      CBS_TRY(lu_solve(n2, X, n2, Bl, n2, n2, info, st));
+      dump("Minv", Bl, (size_t)n2 * n2 * sizeof(c64), st);
+      CBS_TRY(eig(s, n2, Bl, n2, th, vv, n2, info, st));
+      dump("theta", th, (size_t)n2 * sizeof(c64), st);
+      std::vector<c64> hth(n2);
+      CBS_HIP(hipMemcpyAsync(hth.data(), th, n2 * sizeof(c64), hipMemcpyDeviceToHost, st));
+      CBS_HIP(hipStreamSynchronize(st));
+      double thmax = 0;
+      for (auto& t : hth) thmax = std::max(thmax, sqrt(cabs2<double>(t)));
+      // keep finite eigenvalues inside (a slightly widened) annulus; x = top half of v
+      std::vector<int32_t> keep;
+      const double lmin = prm->lambda_min;
+      for (int i = 0; i < n2; ++i) {
+        if (!(sqrt(cabs2<double>(hth[i])) > 1e-13 * thmax)) continue;
+        const c64 lam = cadd<double>(sft, cdiv<double>(make_double2(1, 0), hth[i]));
+        const double a = sqrt(cabs2<double>(lam));
+        if (a > lmin * (1 - 1e-9) && a < (1 + 1e-9) / lmin) {
+          keep.push_back(i);
+          cand.push_back(lam);
+        }
+      }
+      ncand = (int)keep.size();
+      if (ncand > 0) {
+        int32_t* dkeep = nullptr;
+        c64* Xt = nullptr;
+        CBS_TRY(ws_get(ws, "rr.keep", (size_t)ncand, &dkeep));
+        CBS_TRY(ws_get(ws, "rr.Xt", (size_t)m * ncand, &Xt));
+        CBS_HIP(hipMemcpyAsync(dkeep, keep.data(), ncand * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_gather_cols, dim3(launch_grid((int64_t)m * ncand)), dim3(256), 0, st, m, ncand,
+                           (const c64*)vv, n2, (const int32_t*)dkeep, Xt, m);
+        CBS_HIP(hipGetLastError());
+        CBS_TRY(tall_gemm(N, m, ncand, Qa, N, Xt, m, basis, N, st));
+      }
     }
-  }
-  int32_t hinfo[4];
-  CBS_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
-  CBS_HIP(hipStreamSynchronize(st));
-  if (hinfo[0] != 0) {
-    // info[0] = 1: QR iteration did not converge, 2: singular LU pivot, 3: Cholesky QR of
-    // the Ritz basis lost positive definiteness
-    set_error("extraction: %s", hinfo[0] == 1   ? "QR iteration of the reduced eigenproblem did not converge"
-                                : hinfo[0] == 2 ? "the linearised projected QEP is singular at the shift"
-                                                : "Cholesky QR of the Ritz basis failed");
-    return CBS_EEIG;
-  }
-  if (ncand == 0) return CBS_OK;
-  // --- normalise, residuals ||P(lambda) psi||, annulus, sorting
-  double* norms = nullptr;
-  c64* psi = nullptr;
-  c64* Ppsi = nullptr;
-  CBS_TRY(ws_get(ws, "ex.norm", (size_t)ncand, &norms));
-  CBS_TRY(ws_get(ws, "ex.psi", (size_t)ncand * N, &psi));
-  CBS_TRY(ws_get(ws, "ex.Ppsi", (size_t)ncand * N, &Ppsi));
-  CBS_TRY(vec_norms(N, ncand, basis, N, norms, true, psi, N, st));
-  std::vector<c64> c0(ncand, make_double2(1, 0)), cm(ncand);
-  for (int i = 0; i < ncand; ++i) cm[i] = cdiv<double>(make_double2(1, 0), cand[i]);
-  CBS_TRY(apply_parts_dev(s, E, ncand, c0.data(), cand.data(), cm.data(), psi, Ppsi, st));
-  std::vector<double> rn(ncand);
-  CBS_TRY(vec_norms(N, ncand, Ppsi, N, norms, false, nullptr, 0, st));
-  CBS_HIP(hipMemcpyAsync(rn.data(), norms, ncand * sizeof(double), hipMemcpyDeviceToHost, st));
-  CBS_HIP(hipStreamSynchronize(st));
-  if (getenv("CBS_DUMP")) {
-    std::string dir = getenv("CBS_DUMP");
-    FILE* f = fopen((dir + "/cand.txt").c_str(), "w");
-    if (f) {
-      fprintf(f, "info %d %d %d %d\n", hinfo[0], hinfo[1], hinfo[2], hinfo[3]);
-      for (int i = 0; i < ncand; ++i) fprintf(f, "%.17g %.17g %.6e\n", cand[i].x, cand[i].y, rn[i]);
-      fclose(f);
+    int32_t hinfo[4];
+    CBS_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+    CBS_HIP(hipStreamSynchronize(st));
+    if (hinfo[0] != 0) {
+      // info[0] = 1: QR iteration did not converge, 2: singular LU pivot, 3: Cholesky QR of
+      // the Ritz basis lost positive definiteness
+      set_error("extraction: %s", hinfo[0] == 1   ? "QR iteration of the reduced eigenproblem did not converge"
+                                  : hinfo[0] == 2 ? "the linearised projected QEP is singular at the shift"
+                                                  : "Cholesky QR of the Ritz basis failed");
+      return CBS_EEIG;
     }
-  }
-  // operator scale for the spurious-pair filter
-  double cs = std::fabs(s->fd[0]);
-  for (int m2 = 1; m2 <= s->p; ++m2) cs += 2 * std::fabs(s->fd[m2]);
-  const double pscale = 3.0 * 0.5 * cs / (s->h * s->h) + std::fabs(E) + 10.0;
-  const double keep_tol = (prm->extraction == CBS_HANKEL ? 1e-2 : 1e-6) * pscale;
-  std::vector<int> idx;
-  const double lmin = prm->lambda_min;
-  for (int i = 0; i < ncand; ++i) {
-    const double a = sqrt(cabs2<double>(cand[i]));
-    if (!(a > lmin && a < 1.0 / lmin)) continue;   // strict annulus (Eq. 5)
-    if (!(rn[i] <= keep_tol)) continue;
-    idx.push_back(i);
-  }
-  // Order: decay |ln|lambda|| (propagating modes first), then the Bloch phase arg(lambda),
-  // then |lambda| (the inner partner of a pair lambda, 1/conj(lambda) before the outer
-  // one).  Values equal to 1e-9 count as ties, so partners whose |ln|lambda|| differ only
-  // by rounding keep a stable order; insertion sort, which needs no strict weak order.
-  auto before = [&](int a, int b) {
-    const double aa = sqrt(cabs2<double>(cand[a])), ab = sqrt(cabs2<double>(cand[b]));
-    const double la = std::fabs(std::log(aa)), lb = std::fabs(std::log(ab));
-    if (std::fabs(la - lb) > 1e-9 * (1.0 + std::max(la, lb))) return la < lb;
-    const double pa = atan2(cand[a].y, cand[a].x), pb = atan2(cand[b].y, cand[b].x);
-    if (std::fabs(pa - pb) > 1e-9) return pa < pb;
-    return aa < ab;
+    if (ncand == 0) return CBS_OK;
+    // --- normalise, residuals ||P(lambda) psi||, annulus, sorting
+    double* norms = nullptr;
+    c64* psi = nullptr;
+    c64* Ppsi = nullptr;
+    CBS_TRY(ws_get(ws, "ex.norm", (size_t)ncand, &norms));
+    CBS_TRY(ws_get(ws, "ex.psi", (size_t)ncand * N, &psi));
+    CBS_TRY(ws_get(ws, "ex.Ppsi", (size_t)ncand * N, &Ppsi));
+    CBS_TRY(vec_norms(N, ncand, basis, N, norms, true, psi, N, st));
+    std::vector<c64> c0(ncand, make_double2(1, 0)), cm(ncand);
+    for (int i = 0; i < ncand; ++i) cm[i] = cdiv<double>(make_double2(1, 0), cand[i]);
+    CBS_TRY(apply_parts_dev(s, E, ncand, c0.data(), cand.data(), cm.data(), psi, Ppsi, st));
+    std::vector<double> rn(ncand);
+    CBS_TRY(vec_norms(N, ncand, Ppsi, N, norms, false, nullptr, 0, st));
+    CBS_HIP(hipMemcpyAsync(rn.data(), norms, ncand * sizeof(double), hipMemcpyDeviceToHost, st));
+    CBS_HIP(hipStreamSynchronize(st));
+    if (getenv("CBS_DUMP")) {
+      std::string dir = getenv("CBS_DUMP");
+      FILE* f = fopen((dir + "/cand.txt").c_str(), "w");
+      if (f) {
+        fprintf(f, "info %d %d %d %d\n", hinfo[0], hinfo[1], hinfo[2], hinfo[3]);
+        for (int i = 0; i < ncand; ++i) fprintf(f, "%.17g %.17g %.6e\n", cand[i].x, cand[i].y, rn[i]);
+        fclose(f);
+      }
+    }
+    // operator scale for the spurious-pair filter
+    double cs = std::fabs(s->fd[0]);
+    for (int m2 = 1; m2 <= s->p; ++m2) cs += 2 * std::fabs(s->fd[m2]);
+    const double pscale = 3.0 * 0.5 * cs / (s->h * s->h) + std::fabs(E) + 10.0;
+    const double keep_tol = (prm->extraction == CBS_HANKEL ? 1e-2 : 1e-6) * pscale;
+    std::vector<int> idx;
+    const double lmin = prm->lambda_min;
+    for (int i = 0; i < ncand; ++i) {
+      const double a = sqrt(cabs2<double>(cand[i]));
+      if (!(a > lmin && a < 1.0 / lmin)) continue;   // strict annulus (Eq. 5)
+      if (!(rn[i] <= keep_tol)) continue;
+      idx.push_back(i);
+    }
+    // Order: decay |ln|lambda|| (propagating modes first), then the Bloch phase arg(lambda),
+    // then |lambda| (the inner partner of a pair lambda, 1/conj(lambda) before the outer
+    // one).  Values equal to 1e-9 count as ties, so partners whose |ln|lambda|| differ only
+    // by rounding keep a stable order; insertion sort, which needs no strict weak order.
+    auto before = [&](int a, int b) {
+      const double aa = sqrt(cabs2<double>(cand[a])), ab = sqrt(cabs2<double>(cand[b]));
+      const double la = std::fabs(std::log(aa)), lb = std::fabs(std::log(ab));
+      if (std::fabs(la - lb) > 1e-9 * (1.0 + std::max(la, lb))) return la < lb;
+      const double pa = atan2(cand[a].y, cand[a].x), pb = atan2(cand[b].y, cand[b].x);
+      if (std::fabs(pa - pb) > 1e-9) return pa < pb;
+      return aa < ab;
+    };
+    for (size_t i = 1; i < idx.size(); ++i)
+      for (size_t j = i; j > 0 && before(idx[j], idx[j - 1]); --j) std::swap(idx[j], idx[j - 1]);
+    out.lam.resize(idx.size());
+    out.res.resize(idx.size());
+    CBS_TRY(ws_get(ws, out_name, std::max<size_t>(idx.size(), 1) * N, &out.vecs));
+    for (size_t k = 0; k < idx.size(); ++k) {
+      out.lam[k] = cand[idx[k]];
+      out.res[k] = rn[idx[k]];
+      CBS_HIP(hipMemcpyAsync(out.vecs + k * N, psi + (size_t)idx[k] * N, N * sizeof(c64), hipMemcpyDeviceToDevice, st));
+    }
+    CBS_HIP(hipStreamSynchronize(st));
+    return CBS_OK;
   };
-  for (size_t i = 1; i < idx.size(); ++i)
-    for (size_t j = i; j > 0 && before(idx[j], idx[j - 1]); --j) std::swap(idx[j], idx[j - 1]);
-  out.lam.resize(idx.size());
-  out.res.resize(idx.size());
-  CBS_TRY(ws_get(ws, "ex.out", std::max<size_t>(idx.size(), 1) * N, &out.vecs));
-  for (size_t k = 0; k < idx.size(); ++k) {
-    out.lam[k] = cand[idx[k]];
-    out.res[k] = rn[idx[k]];
-    CBS_HIP(hipMemcpyAsync(out.vecs + k * N, psi + (size_t)idx[k] * N, N * sizeof(c64), hipMemcpyDeviceToDevice, st));
+  CBS_TRY(extract_rank(m_hi, "ex.out", out));
+  if (m_lo != m_hi) {
+    Extracted alt;
+    CBS_TRY(extract_rank(m_lo, "ex.out2", alt));
+    auto worst = [](const Extracted& x) {
+      double w = 0;
+      for (double r : x.res) w = std::max(w, r);
+      return w;
+    };
+    if (alt.lam.size() > out.lam.size() || (alt.lam.size() == out.lam.size() && worst(alt) < worst(out)))
+      out = std::move(alt);
   }
-  CBS_HIP(hipStreamSynchronize(st));
   return CBS_OK;
 }
 
@@ -605,7 +648,7 @@ extern "C" int32_t cbs_solve(cbs_system* s, double E, const cbs_params* prm, con
   Extracted ex;
   double tmom = 0;
   auto t0 = std::chrono::steady_clock::now();
-  CBS_TRY(extract(s, E, prm, Vc, ns.Y, nqs, st, ex, &tmom));
+  CBS_TRY(extract(s, E, prm, solve_noise(ns.relres, 0, ns.nruns), Vc, ns.Y, nqs, st, ex, &tmom));
   auto t1 = std::chrono::steady_clock::now();
   CBS_TRY(store_last(s, E, ex, st));
   const int cnt = (int)ex.lam.size();
@@ -776,7 +819,8 @@ static int32_t solve_batched_queue(int32_t n_sys, cbs_system* const* systems, in
       double tmom = 0;
       auto t0 = std::chrono::steady_clock::now();
       const c64* Se = q.S + (size_t)e * M2 * L * sy->N;
-      const int32_t rc = extract_S(sy, E[e], prm, (const c64*)V[s], Se, st, ex, &tmom, t0);
+      const int32_t rc = extract_S(sy, E[e], prm, solve_noise(rr, (int64_t)e * nq * L, (int64_t)(e + 1) * nq * L),
+                                   (const c64*)V[s], Se, st, ex, &tmom, t0);
       if (rc == CBS_EHIP || rc == CBS_ENOMEM || rc == CBS_EINVAL) return rc;
       bool noconv = false, brk = false;
       double mx = 0, sum = 0;
@@ -941,7 +985,9 @@ extern "C" int32_t cbs_solve_batched(int32_t n_sys, cbs_system* const* systems, 
         double tmom = 0;
         auto t0 = std::chrono::steady_clock::now();
         const Pair<double>* Ye = ns.Y + (size_t)e * nq * L * sy->N;
-        const int32_t rc = extract(sy, E[e0 + e], prm, (const c64*)V[s], Ye, nq, st, ex, &tmom);
+        const int32_t rc = extract(sy, E[e0 + e], prm,
+                                   solve_noise(ns.relres, (int64_t)e * nq * L, (int64_t)(e + 1) * nq * L),
+                                   (const c64*)V[s], Ye, nq, st, ex, &tmom);
         if (rc == CBS_EHIP || rc == CBS_ENOMEM || rc == CBS_EINVAL) return rc;
         if (rc != CBS_OK) {
           // this pair has no eigenpairs (non-finite moments or a failed dense step); the

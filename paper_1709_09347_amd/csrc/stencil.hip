@@ -612,8 +612,11 @@ static int32_t tune_nonlocal(cbs_system* s, hipStream_t st, bool tune_update, st
 
 // CBS_BRA_TILE=<runs>[:<points>] fixes the full-batch bra after tuning: runs 0 = per atom,
 // 4 or 8 = chunked with that many runs per workgroup, on chunks of 256 or 512 points
-// (default 512).
+// (default 512); CBS_BRA_NW (4 or 8) and CBS_BRA_SPREAD (0 or 1) fix the per-atom bra's
+// waves and workgroup order.
 static int32_t bra_override(cbs_system* s) {
+  if (const char* w = getenv("CBS_BRA_NW")) s->bra_nw[0] = s->bra_nw[1] = atoi(w) == 8 ? 8 : 4;
+  if (const char* w = getenv("CBS_BRA_SPREAD")) s->bra_spread[0] = s->bra_spread[1] = atoi(w) != 0;
   const char* e = getenv("CBS_BRA_TILE");
   if (e == nullptr || e[0] == 0) return CBS_OK;
   const int rg = atoi(e);

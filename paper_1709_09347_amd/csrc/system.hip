@@ -40,6 +40,14 @@ int32_t Workspace::get(const char* name, size_t bytes, void** out) {
       return CBS_ENOMEM;
     }
     b.bytes = bytes;
+    // CBS_WS_POISON=1 fills new workspace with NaN bytes (a check that no kernel reads a
+    // workspace buffer before writing it)
+    if (const char* e = getenv("CBS_WS_POISON")) {
+      if (e[0] == '1' && hipMemset(b.p, 0xFF, bytes) != hipSuccess) {
+        set_error("poisoning workspace '%s' failed", name);
+        return CBS_EHIP;
+      }
+    }
   }
   *out = b.p;
   return CBS_OK;
@@ -186,7 +194,7 @@ static int32_t build_projectors(cbs_system* s, const cbs_proj* pr) {
   // pieces allowed is left out (the per-atom bra remains)
   for (int ti = 0; ti < 2; ++ti) {
     BraTileTables bt;
-    if (!build_bra_tile_tables(s->N, A, seg, idx, u64, BT_TPS[ti], BT_MAXP, bt).empty() || bt.key_slot.empty())
+    if (!build_bra_tile_tables(s->N, A, seg, idx, u64, BT_TPS[ti], BT_MAXP, BT_EB, bt).empty() || bt.key_slot.empty())
       continue;
     ChunkTables& d = P.bt[ti];
     std::vector<float> btu32(bt.ent_u.begin(), bt.ent_u.end());
@@ -198,8 +206,10 @@ static int32_t build_projectors(cbs_system* s, const cbs_proj* pr) {
     CBS_TRY(upload(bt.ent_pt, &d.ent_pt));
     CBS_TRY(upload(bt.ent_u, &d.u64));
     CBS_TRY(upload(btu32, &d.u32));
+    std::vector<int32_t> pos(bt.key_slot.size());
+    for (size_t t = 0; t < pos.size(); ++t) pos[bt.key_slot[t]] = (int32_t)t;
     CBS_TRY(upload(bt.key_off, &d.key_off));
-    CBS_TRY(upload(bt.key_slot, &d.key_slot));
+    CBS_TRY(upload(pos, &d.slot_pos));
     d.tp = BT_TPS[ti];
     d.nchunks = bt.nchunks;
     d.nslots = (int32_t)bt.key_slot.size();
@@ -254,7 +264,7 @@ static void free_system(cbs_system* s) {
     f(d.u64);
     f(d.u32);
     f(d.key_off);
-    f(d.key_slot);
+    f(d.slot_pos);
   }
   f(s->last.vecs);
   s->ws.release();

@@ -73,22 +73,26 @@ inline std::string build_group_tables(int64_t n_points, const std::vector<int32_
 // are cut into pieces of consecutive entries and nearly equal size: per chunk the smallest
 // piece length for which the chunk has at most max_pieces pieces (pl: the longest piece).
 //   piece_off[c]..piece_off[c+1]   pieces of chunk c (global piece numbers)
-//   piece_beg[q], piece_meta[q]    first entry of piece q; (local slot << 16) | entry count
+//   piece_beg[q], piece_meta[q]    first entry of piece q; (local slot << 16) | entry count,
+//                                  the count padded to a multiple of pad with entries of
+//                                  point 0 and zero values (piece_real[q]: the count before)
 //   slot_off[c]..slot_off[c+1]     slots of chunk c
 //   slot_piece[g]..slot_piece[g+1] pieces of slot g
-//   ent_pt[e], ent_u[4e..]         reordered entries: point offset within the chunk, values
+//   ent_pt[e], ent_u[4e..]         reordered (and padded) entries: point offset within the
+//                                  chunk, values
 //   key_off[k]..key_off[k+1]       slots of key k (ascending, i.e. in chunk order) in key_slot
 struct BraTileTables {
   int32_t tp = 0, pl = 0, nchunks = 0, max_pieces = 0, max_slots = 0;
-  std::vector<int32_t> piece_off, piece_beg, piece_meta, slot_off, slot_piece, ent_pt, key_off, key_slot;
+  std::vector<int32_t> piece_off, piece_beg, piece_meta, piece_real, slot_off, slot_piece, ent_pt, key_off,
+      key_slot;
   std::vector<double> ent_u;
 };
 
 // Returns an empty string on success, else the reason.
 inline std::string build_bra_tile_tables(int64_t n_points, int32_t n_atoms, const std::vector<int32_t>& seg,
                                          const std::vector<int32_t>& idx, const std::vector<double>& u, int tp,
-                                         int max_pieces, BraTileTables& t) {
-  if (tp < 1 || max_pieces < 1) return "bra tile table: bad chunk or piece limit";
+                                         int max_pieces, int pad, BraTileTables& t) {
+  if (tp < 1 || max_pieces < 1 || pad < 1) return "bra tile table: bad chunk, piece or padding size";
   const int64_t nnz = (int64_t)idx.size();
   const int64_t nchunks = (n_points + tp - 1) / tp;
   if (nchunks >= ((int64_t)1 << 31)) return "bra tile table: too many chunks";
@@ -135,6 +139,9 @@ inline std::string build_bra_tile_tables(int64_t n_points, int32_t n_atoms, cons
   t.piece_off.assign(nchunks + 1, 0);
   t.piece_beg.clear();
   t.piece_meta.clear();
+  t.piece_real.clear();
+  t.ent_pt.clear();
+  t.ent_u.clear();
   t.slot_piece.assign(nslots + 1, 0);
   t.pl = 0;
   t.max_pieces = 0;
@@ -154,31 +161,36 @@ inline std::string build_bra_tile_tables(int64_t n_points, int32_t n_atoms, cons
       else lo = mid + 1;
     }
     const int64_t lc = lo;
-    if (lc >= (1 << 16)) return "bra tile table: a piece would exceed 65535 entries";
+    if (lc + pad >= (1 << 16)) return "bra tile table: a piece would exceed 65535 entries";
     for (int32_t g = g0; g < g1; ++g) {
       t.slot_piece[g] = (int32_t)t.piece_beg.size();
       const int64_t n = slot_beg[g + 1] - slot_beg[g];
       const int64_t np = (n + lc - 1) / lc;
       for (int64_t q = 0; q < np; ++q) {
         const int64_t b = slot_beg[g] + n * q / np, e = slot_beg[g] + n * (q + 1) / np;
-        t.piece_beg.push_back((int32_t)b);
-        t.piece_meta.push_back(((g - g0) << 16) | (int32_t)(e - b));
-        t.pl = std::max<int32_t>(t.pl, (int32_t)(e - b));
+        const int64_t padded = (e - b + pad - 1) / pad * pad;
+        t.piece_beg.push_back((int32_t)t.ent_pt.size());
+        t.piece_meta.push_back(((g - g0) << 16) | (int32_t)padded);
+        t.piece_real.push_back((int32_t)(e - b));
+        t.pl = std::max<int32_t>(t.pl, (int32_t)padded);
+        for (int64_t i = b; i < b + padded; ++i) {
+          if (i < e) {
+            const int32_t en = order[i];
+            t.ent_pt.push_back((int32_t)(idx[en] - (int64_t)(idx[en] / tp) * tp));
+            for (int k = 0; k < 4; ++k) t.ent_u.push_back(u[4 * (size_t)en + k]);
+          } else {
+            t.ent_pt.push_back(0);
+            for (int k = 0; k < 4; ++k) t.ent_u.push_back(0.0);
+          }
+        }
       }
     }
     t.piece_off[c + 1] = (int32_t)t.piece_beg.size();
     t.max_pieces = std::max<int32_t>(t.max_pieces, t.piece_off[c + 1] - t.piece_off[c]);
   }
   t.slot_piece[nslots] = (int32_t)t.piece_beg.size();
-  if (t.piece_beg.size() >= ((size_t)1 << 31)) return "bra tile table: too many pieces";
-  // entries
-  t.ent_pt.resize(nnz);
-  t.ent_u.resize(4 * (size_t)nnz);
-  for (int64_t i = 0; i < nnz; ++i) {
-    const int32_t e = order[i];
-    t.ent_pt[i] = (int32_t)(idx[e] - (int64_t)(idx[e] / tp) * tp);
-    for (int k = 0; k < 4; ++k) t.ent_u[4 * (size_t)i + k] = u[4 * (size_t)e + k];
-  }
+  if (t.piece_beg.size() >= ((size_t)1 << 31) || t.ent_pt.size() >= ((size_t)1 << 31))
+    return "bra tile table: too many pieces or entries";
   // slots of each key, in chunk order
   t.key_off.assign(nkeys + 1, 0);
   for (int64_t g = 0; g < nslots; ++g) t.key_off[slot_key[g] + 1]++;

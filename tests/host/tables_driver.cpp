@@ -5,10 +5,10 @@
 //   int32 pt_key[nnz], double pt_u[4*nnz];
 //   output: for each table, int64 length then the values (grp_off, grp_key, grp_u, grp_mask).
 // Chunked bra table (argv: bra in out):
-//   input: int64 n_points, int32 n_atoms, int32 tp, int32 max_pieces, int64 nnz,
+//   input: int64 n_points, int32 n_atoms, int32 tp, int32 max_pieces, int32 pad, int64 nnz,
 //   int32 seg[4*n_atoms], int32 idx[nnz], double u[4*nnz];
-//   output: the same framing for piece_off, piece_beg, piece_meta, slot_off, slot_piece,
-//   ent_pt, ent_u, key_off, key_slot, then {pl, max_pieces, max_slots}.
+//   output: the same framing for piece_off, piece_beg, piece_meta, piece_real, slot_off,
+//   slot_piece, ent_pt, ent_u, key_off, key_slot, then {pl, max_pieces, max_slots}.
 // On failure the reason on stderr, exit 2.
 #include <cstdio>
 #include <cstring>
@@ -57,16 +57,16 @@ static int bra(const char* in, const char* out) {
   FILE* f = fopen(in, "rb");
   if (!f) return 1;
   long long np = 0, nnz = 0;
-  int na = 0, tp = 0, maxp = 0;
+  int na = 0, tp = 0, maxp = 0, pad = 0;
   if (fread(&np, 8, 1, f) != 1 || fread(&na, 4, 1, f) != 1 || fread(&tp, 4, 1, f) != 1 ||
-      fread(&maxp, 4, 1, f) != 1 || fread(&nnz, 8, 1, f) != 1)
+      fread(&maxp, 4, 1, f) != 1 || fread(&pad, 4, 1, f) != 1 || fread(&nnz, 8, 1, f) != 1)
     return 1;
   std::vector<int32_t> seg, idx;
   std::vector<double> u;
   if (!rd(f, seg, 4 * (size_t)na) || !rd(f, idx, nnz) || !rd(f, u, 4 * nnz)) return 1;
   fclose(f);
   cbs::BraTileTables t;
-  const std::string why = cbs::build_bra_tile_tables(np, na, seg, idx, u, tp, maxp, t);
+  const std::string why = cbs::build_bra_tile_tables(np, na, seg, idx, u, tp, maxp, pad, t);
   if (!why.empty()) {
     fprintf(stderr, "%s\n", why.c_str());
     return 2;
@@ -75,6 +75,7 @@ static int bra(const char* in, const char* out) {
   wr(o, t.piece_off);
   wr(o, t.piece_beg);
   wr(o, t.piece_meta);
+  wr(o, t.piece_real);
   wr(o, t.slot_off);
   wr(o, t.slot_piece);
   wr(o, t.ent_pt);

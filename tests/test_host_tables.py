@@ -127,11 +127,11 @@ def _atom_major(sysw):
     return np.array(seg, np.int32), np.concatenate(idx), np.concatenate(vals)
 
 
-def _run_bra(driver, tmp_path, n, n_atoms, seg, idx, vals, tp, max_pieces):
+def _run_bra(driver, tmp_path, n, n_atoms, seg, idx, vals, tp, max_pieces, pad):
     inp = tmp_path / "bra_in.bin"
     with open(inp, "wb") as f:
         np.array([n], np.int64).tofile(f)
-        np.array([n_atoms, tp, max_pieces], np.int32).tofile(f)
+        np.array([n_atoms, tp, max_pieces, pad], np.int32).tofile(f)
         np.array([len(idx)], np.int64).tofile(f)
         seg.astype(np.int32).tofile(f)
         idx.astype(np.int32).tofile(f)
@@ -141,8 +141,8 @@ def _run_bra(driver, tmp_path, n, n_atoms, seg, idx, vals, tp, max_pieces):
     if r.returncode != 0:
         return None, r.stderr
     data = open(out, "rb").read()
-    names = ["piece_off", "piece_beg", "piece_meta", "slot_off", "slot_piece", "ent_pt", "ent_u", "key_off",
-             "key_slot", "scalars"]
+    names = ["piece_off", "piece_beg", "piece_meta", "piece_real", "slot_off", "slot_piece", "ent_pt", "ent_u",
+             "key_off", "key_slot", "scalars"]
     tabs, pos = {}, 0
     for nm in names:
         dt = np.float64 if nm == "ent_u" else np.int32
@@ -153,82 +153,92 @@ def _run_bra(driver, tmp_path, n, n_atoms, seg, idx, vals, tp, max_pieces):
     return tabs, ""
 
 
-@pytest.mark.parametrize("case,tp", [("tiny", 64), ("tiny", 7), ("tiny", 512), ("cfg2", 256), ("cfg2", 512)])
-def test_chunked_bra_table(driver, tmp_path, case, tp):
+@pytest.mark.parametrize("case,tp,pad", [("tiny", 64, 4), ("tiny", 7, 1), ("tiny", 512, 3), ("cfg2", 256, 4),
+                                         ("cfg2", 512, 4)])
+def test_chunked_bra_table(driver, tmp_path, case, tp, pad):
     sysw = {"tiny": lambda: W.tiny(with_proj=True, fd_order=8),
             "cfg2": lambda: W.config(2).systems[0]}[case]()
     n, na = sysw.n, sysw.proj.n_atoms
     seg, idx, vals = _atom_major(sysw)
-    max_pieces = 64
-    t, err = _run_bra(driver, tmp_path, n, na, seg, idx, vals, tp, max_pieces)
+    max_pieces = 128
+    t, err = _run_bra(driver, tmp_path, n, na, seg, idx, vals, tp, max_pieces, pad)
     assert t is not None, err
     pl, worst, max_slots = (int(x) for x in t["scalars"])
     nch = (n + tp - 1) // tp
-    po, pbeg, pmeta, so, sp = t["piece_off"], t["piece_beg"], t["piece_meta"], t["slot_off"], t["slot_piece"]
+    po, pbeg, pmeta, preal = t["piece_off"], t["piece_beg"], t["piece_meta"], t["piece_real"]
+    so, sp = t["slot_off"], t["slot_piece"]
     ent_pt, ent_u = t["ent_pt"], t["ent_u"].reshape(-1, 4)
     key_off, key_slot = t["key_off"], t["key_slot"]
     nslots = len(key_slot)
     assert len(po) == nch + 1 and len(so) == nch + 1 and so[-1] == nslots and len(sp) == nslots + 1
-    assert po[0] == 0 and np.all(np.diff(po) >= 0) and po[-1] == len(pbeg) == sp[-1]
-    # pieces: at most pl entries, at most max_pieces per chunk
+    assert po[0] == 0 and np.all(np.diff(po) >= 0) and po[-1] == len(pbeg) == sp[-1] == len(preal)
+    # pieces: counts padded to a multiple of pad, at most max_pieces per chunk
     cnt = pmeta & 0xFFFF
-    assert np.all(cnt >= 1) and cnt.max() == pl
-    assert np.diff(po).max() == worst <= max_pieces
-    # key of every reordered entry, from the slot its piece belongs to
+    assert np.all(preal >= 1) and np.all(cnt % pad == 0) and np.all((cnt >= preal) & (cnt < preal + pad))
+    assert cnt.max() == pl and np.diff(po).max() == worst <= max_pieces
+    assert pbeg[0] == 0 and np.all(pbeg[1:] == pbeg[:-1] + cnt[:-1]) and pbeg[-1] + cnt[-1] == len(ent_pt)
+    # key of every reordered entry, from the slot its piece belongs to; padding marked -2
     key_of_slot = np.empty(nslots, np.int64)
     for k in range(3 * na):
         key_of_slot[key_slot[key_off[k]:key_off[k + 1]]] = k
     chunk_of_slot = np.repeat(np.arange(nch), np.diff(so))
-    ent_key = np.full(len(idx), -1, np.int64)
-    ent_chunk = np.full(len(idx), -1, np.int64)
+    ent_key = np.full(len(ent_pt), -1, np.int64)
+    ent_chunk = np.full(len(ent_pt), -1, np.int64)
     for c in range(nch):
         for q in range(po[c], po[c + 1]):
             ls = pmeta[q] >> 16
             g = so[c] + ls
             assert so[c] <= g < so[c + 1] and sp[g] <= q < sp[g + 1]
-            assert np.all(ent_key[pbeg[q]:pbeg[q] + cnt[q]] == -1)   # pieces do not overlap
-            ent_key[pbeg[q]:pbeg[q] + cnt[q]] = key_of_slot[g]
-            ent_chunk[pbeg[q]:pbeg[q] + cnt[q]] = c
-        # the pieces of a slot are consecutive, cover its entries in order and differ in
-        # size by at most one; one piece fewer per slot would have been too long: the
-        # chunk's pieces are as short as the limit allows
-        lc = cnt[po[c]:po[c + 1]].max() if po[c + 1] > po[c] else 0
+            ent_key[pbeg[q]:pbeg[q] + preal[q]] = key_of_slot[g]
+            ent_chunk[pbeg[q]:pbeg[q] + preal[q]] = c
+            ent_key[pbeg[q] + preal[q]:pbeg[q] + cnt[q]] = -2
+        # the pieces of a slot are consecutive and differ in size by at most one; one piece
+        # fewer per slot would have been too long: the chunk's pieces are as short as the
+        # limit allows
+        lc = preal[po[c]:po[c + 1]].max() if po[c + 1] > po[c] else 0
         for g in range(so[c], so[c + 1]):
             qs = np.arange(sp[g], sp[g + 1])
-            assert len(qs) >= 1 and np.all(pbeg[qs[1:]] == pbeg[qs[:-1]] + cnt[qs[:-1]])
-            assert cnt[qs].max() - cnt[qs].min() <= 1
+            assert len(qs) >= 1 and preal[qs].max() - preal[qs].min() <= 1
         if lc > 1:
-            sizes = np.array([cnt[sp[g]:sp[g + 1]].sum() for g in range(so[c], so[c + 1])])
+            sizes = np.array([preal[sp[g]:sp[g + 1]].sum() for g in range(so[c], so[c + 1])])
             assert np.sum(-(-sizes // (lc - 1))) > max_pieces
-    assert np.all(ent_key >= 0), "every entry lies in one piece"
-    for c in range(nch):   # slots of a chunk by ascending key
-        assert np.all(np.diff(key_of_slot[so[c]:so[c + 1]]) > 0)
+        assert np.all(np.diff(key_of_slot[so[c]:so[c + 1]]) > 0)   # slots of a chunk by ascending key
+    assert np.all(ent_key != -1), "every entry lies in one piece"
+    pad_e = ent_key == -2
+    assert np.all(ent_pt[pad_e] == 0) and np.all(ent_u[pad_e] == 0)
+    real = ~pad_e
+    assert real.sum() == len(idx)
     for k in range(3 * na):   # slots of a key in chunk order
         assert np.all(np.diff(chunk_of_slot[key_slot[key_off[k]:key_off[k + 1]]]) > 0)
-    assert np.all((ent_pt >= 0) & (ent_pt < tp)) and np.all(ent_chunk * tp + ent_pt < n)
+    assert np.all((ent_pt >= 0) & (ent_pt < tp)) and np.all(ent_chunk[real] * tp + ent_pt[real] < n)
     # the same multiset of (point, key, values) as the input
     key_in = np.concatenate([np.full(seg[4 * a + s + 1] - seg[4 * a + s], 3 * a + s)
                              for a in range(na) for s in range(3)])
     a_in = np.lexsort((vals[:, 3], vals[:, 2], vals[:, 1], vals[:, 0], idx, key_in))
-    pt_out = ent_chunk * tp + ent_pt
-    a_out = np.lexsort((ent_u[:, 3], ent_u[:, 2], ent_u[:, 1], ent_u[:, 0], pt_out, ent_key))
-    np.testing.assert_array_equal(key_in[a_in], ent_key[a_out])
+    pt_out = (ent_chunk * tp + ent_pt)[real]
+    u_out, k_out = ent_u[real], ent_key[real]
+    a_out = np.lexsort((u_out[:, 3], u_out[:, 2], u_out[:, 1], u_out[:, 0], pt_out, k_out))
+    np.testing.assert_array_equal(key_in[a_in], k_out[a_out])
     np.testing.assert_array_equal(idx[a_in], pt_out[a_out])
-    np.testing.assert_array_equal(vals[a_in], ent_u[a_out])
-    # the bra through the tables (chunk sums added per key in chunk order) equals the
-    # direct per-segment sums; integer values keep both sums exact
+    np.testing.assert_array_equal(vals[a_in], u_out[a_out])
+    # the bra through the tables (every piece entry, padding included, then the chunk sums
+    # added per key in chunk order) equals the direct per-segment sums; integer values keep
+    # both sums exact
     rng = np.random.default_rng(3)
     x = rng.integers(-8, 9, size=n).astype(np.float64)
     ui = np.round(vals * 16)
     direct = np.zeros((3 * na, 4))
     np.add.at(direct, key_in, ui * x[idx][:, None])
-    ui_out = np.zeros_like(ent_u)
-    ui_out[a_out] = ui[a_in]
+    ui_all = np.zeros_like(ent_u)
+    real_idx = np.flatnonzero(real)
+    ui_all[real_idx[a_out]] = ui[a_in]
+    chunk_pt = np.repeat(np.arange(nch), np.diff(so))   # chunk of each slot
     chunk_sum = np.zeros((nslots, 4))
     for g in range(nslots):
+        base = chunk_pt[g] * tp
         for q in range(sp[g], sp[g + 1]):
             e = np.arange(pbeg[q], pbeg[q] + cnt[q])
-            chunk_sum[g] += (ui_out[e] * x[pt_out[e]][:, None]).sum(axis=0)
+            chunk_sum[g] += (ui_all[e] * x[np.minimum(base + ent_pt[e], n - 1)][:, None]).sum(axis=0)
     via = np.array([chunk_sum[key_slot[key_off[k]:key_off[k + 1]]].sum(axis=0) for k in range(3 * na)])
     np.testing.assert_array_equal(via, direct)
 
@@ -236,5 +246,5 @@ def test_chunked_bra_table(driver, tmp_path, case, tp):
 def test_chunked_bra_table_refuses_too_many_keys(driver, tmp_path):
     sysw = W.config(2).systems[0]
     seg, idx, vals = _atom_major(sysw)
-    t, err = _run_bra(driver, tmp_path, sysw.n, sysw.proj.n_atoms, seg, idx, vals, 512, 8)
+    t, err = _run_bra(driver, tmp_path, sysw.n, sysw.proj.n_atoms, seg, idx, vals, 512, 8, 4)
     assert t is None and "keys in a chunk" in err
