@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "cbs_internal.hpp"
@@ -348,6 +349,140 @@ __global__ void __launch_bounds__(JWG) k_jacobi_svd(int32_t n, c64* A, int32_t l
   }
 }
 
+// ------------------------------------------------------------------ block one-sided Jacobi SVD
+// The same factorisation A W = U Sigma, with the columns in nb blocks of bs: blocks are
+// paired round-robin (as the columns above), one workgroup per block pair copies the pair's
+// 2 bs columns of A and of W into LDS, runs one full one-sided Jacobi sweep over them (every
+// column pair, round-robin inside the pair) and writes them back.  nb - 1 launches make an
+// outer sweep; the largest |a_p^H a_q| / (|a_p| |a_q|) of the sweep decides convergence.  The
+// single-workgroup kernel above moves both matrices through one CU's caches every round;
+// here the rotations run in LDS on nb / 2 CUs.
+__global__ void k_svd_init(int32_t n, c64* V, int32_t ldv, unsigned long long* flag) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n * n; t += gridDim.x * blockDim.x) {
+    const int i = t % n, j = t / n;
+    V[i + (int64_t)j * ldv] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0ull;
+}
+
+// slot k of nslots after r rotations holds: slot 0 item 0, slot k >= 1 item
+// 1 + ((k - 1 - r) mod (nslots - 1))
+__device__ __forceinline__ int rr_slot(int k, int r, int nslots) {
+  if (k == 0) return 0;
+  int c = (k - 1 - r) % (nslots - 1);
+  if (c < 0) c += nslots - 1;
+  return 1 + c;
+}
+
+constexpr int BJ_THREADS = 1024;
+constexpr size_t BJ_LDS = 128 * 1024;   // the block pair's columns of A and W
+
+__global__ void __launch_bounds__(BJ_THREADS) k_svd_block(int32_t n, int32_t bs, int32_t nb, int32_t round, c64* A,
+                                                          int32_t lda, c64* V, int32_t ldv,
+                                                          unsigned long long* flag) {
+  __shared__ c64 bj_lds[BJ_LDS / sizeof(c64)];
+  __shared__ double sh[BJ_THREADS / 64];
+  c64* la = bj_lds;                       // [2 bs][n]
+  c64* lv = la + (size_t)2 * bs * n;      // [2 bs][n]
+  int bp = rr_slot(blockIdx.x, round, nb), bq = rr_slot(nb - 1 - blockIdx.x, round, nb);
+  const int tid = threadIdx.x;
+  const int cols = 2 * bs;
+  // local column c: block bp's columns first, then bq's; columns at or past n are padding
+  auto gcol = [&](int c) { return (c < bs) ? bp * bs + c : bq * bs + (c - bs); };
+  for (int t = tid; t < cols * n; t += BJ_THREADS) {
+    const int c = t / n, i = t - c * n;
+    const int g = gcol(c);
+    la[t] = (g < n) ? A[i + (int64_t)g * lda] : make_double2(0, 0);
+    lv[t] = (g < n) ? V[i + (int64_t)g * ldv] : make_double2(0, 0);
+  }
+  __syncthreads();
+  // threads per column pair: a power of two up to 64 (one wave), bs pairs per inner round
+  int gsize = 64;
+  while (gsize * bs > BJ_THREADS) gsize >>= 1;
+  const int pidx = tid / gsize, sub = tid % gsize;
+  double offmax = 0;
+  for (int ir = 0; ir < cols - 1; ++ir) {
+    if (pidx < bs) {
+      int p = rr_slot(pidx, ir, cols), q = rr_slot(cols - 1 - pidx, ir, cols);
+      if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+      }
+      const bool valid = gcol(p) < n && gcol(q) < n;
+      c64* ap = la + (size_t)p * n;
+      c64* aq = la + (size_t)q * n;
+      double al = 0, be = 0;
+      c64 ga = make_double2(0, 0);
+      if (valid) {
+        for (int i = sub; i < n; i += gsize) {
+          const c64 x = ap[i], y = aq[i];
+          al += cabs2<double>(x);
+          be += cabs2<double>(y);
+          ga = zadd(ga, zmulc(x, y));
+        }
+      }
+      for (int o = 1; o < gsize; o <<= 1) {
+        al += __shfl_xor(al, o, 64);
+        be += __shfl_xor(be, o, 64);
+        ga.x += __shfl_xor(ga.x, o, 64);
+        ga.y += __shfl_xor(ga.y, o, 64);
+      }
+      const double g = zabs(ga);
+      if (valid && g > 1e-15 * sqrt(al * be) && g != 0.0) {
+        offmax = fmax(offmax, g / sqrt(al * be));
+        const double zeta = (be - al) / (2.0 * g);
+        const double t = ((zeta >= 0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        const c64 e = make_double2(ga.x / g, -ga.y / g);   // e^{-i phi}
+        c64* vp = lv + (size_t)p * n;
+        c64* vq = lv + (size_t)q * n;
+        for (int i = sub; i < n; i += gsize) {
+          const c64 x = ap[i], y = zmul(e, aq[i]);
+          ap[i] = zsub(zscale(x, c), zscale(y, sn));
+          aq[i] = zadd(zscale(x, sn), zscale(y, c));
+          const c64 u = vp[i], w = zmul(e, vq[i]);
+          vp[i] = zsub(zscale(u, c), zscale(w, sn));
+          vq[i] = zadd(zscale(u, sn), zscale(w, c));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < cols * n; t += BJ_THREADS) {
+    const int c = t / n, i = t - c * n;
+    const int g = gcol(c);
+    if (g < n) {
+      A[i + (int64_t)g * lda] = la[t];
+      V[i + (int64_t)g * ldv] = lv[t];
+    }
+  }
+  const double om = block_max_wg<BJ_THREADS>(offmax, sh);
+  // values are non-negative, so their bit patterns order like the values
+  if (tid == 0 && om > 0) atomicMax(flag, (unsigned long long)__double_as_longlong(om));
+}
+
+// column norms, sigma sorted descending with its permutation, U columns normalised (the
+// tail of the single-workgroup kernel)
+__global__ void __launch_bounds__(JWG) k_svd_finish(int32_t n, c64* A, int32_t lda, double* sigma, int32_t* perm) {
+  const int tid = threadIdx.x;
+  for (int j = tid; j < n; j += JWG) {
+    double s2 = 0;
+    for (int i = 0; i < n; ++i) s2 += cabs2<double>(A[i + (int64_t)j * lda]);
+    sigma[512 + j] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += JWG) perm[desc_rank(n, sigma + 512, j)] = j;
+  __syncthreads();
+  for (int r = tid; r < n; r += JWG) sigma[r] = sigma[512 + perm[r]];
+  __syncthreads();
+  for (int j = tid; j < n; j += JWG) {
+    const double sj = sigma[512 + j];
+    if (sj > 0)
+      for (int i = 0; i < n; ++i) A[i + (int64_t)j * lda] = zscale(A[i + (int64_t)j * lda], 1.0 / sj);
+  }
+}
+
 // ------------------------------------------------------------------ small GEMM (one workgroup)
 // C = op(A) * B (+ scale of columns), op = identity or conjugate transpose.
 __global__ void __launch_bounds__(SWG) k_small_gemm(int32_t m, int32_t n, int32_t k, const c64* A, int32_t lda,
@@ -616,7 +751,39 @@ int32_t svd(int32_t n, c64* A, int32_t lda, c64* V, int32_t ldv, double* sigma, 
     set_error("svd: order %d above 512", n);
     return CBS_EINVAL;
   }
-  hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(JWG), 0, st, n, A, lda, V, ldv, sigma, perm, 60);
+  if (n < 4 || getenv("CBS_SVD_SINGLE")) {
+    hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(JWG), 0, st, n, A, lda, V, ldv, sigma, perm, 60);
+    CBS_HIP(hipGetLastError());
+    return CBS_OK;
+  }
+  // block size: the pair's 2 bs columns of A and W in at most 128 KB of LDS, at least 2
+  // blocks; an odd block count gets a padding block
+  int bs = 1;
+  while (bs * 2 * (int64_t)n * 2 * 2 * sizeof(c64) <= BJ_LDS && bs * 2 * 2 <= n) bs *= 2;
+  int nb = (n + bs - 1) / bs;
+  nb += nb & 1;
+  unsigned long long* flag = nullptr;
+  CBS_HIP(hipMalloc(&flag, sizeof(unsigned long long)));
+  struct Free {
+    unsigned long long* p;
+    ~Free() { (void)hipFree(p); }
+  } fr{flag};
+  hipLaunchKernelGGL(k_svd_init, dim3(std::min(1024, (n * n + 255) / 256)), dim3(256), 0, st, n, V, ldv, flag);
+  CBS_HIP(hipGetLastError());
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    for (int r = 0; r < nb - 1; ++r) {
+      hipLaunchKernelGGL(k_svd_block, dim3(nb / 2), dim3(BJ_THREADS), 0, st, n, bs, nb, r, A, lda, V, ldv, flag);
+      CBS_HIP(hipGetLastError());
+    }
+    unsigned long long h = 0;
+    CBS_HIP(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, st));
+    CBS_HIP(hipStreamSynchronize(st));
+    double om = 0;
+    std::memcpy(&om, &h, sizeof(om));
+    if (!(om >= 1e-13)) break;   // converged (or nothing rotated)
+    CBS_HIP(hipMemsetAsync(flag, 0, sizeof(unsigned long long), st));
+  }
+  hipLaunchKernelGGL(k_svd_finish, dim3(1), dim3(JWG), 0, st, n, A, lda, sigma, perm);
   CBS_HIP(hipGetLastError());
   return CBS_OK;
 }

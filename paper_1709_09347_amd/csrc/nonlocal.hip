@@ -496,14 +496,15 @@ __global__ void __launch_bounds__(256) k_bra_fin(BraFinArgs<R, C> a) {
     C sum = 0;
     const C* pr = a.part + (int64_t)run * a.nslots * 16 + k;
     const int t0 = a.key_off[key], t1 = a.key_off[key + 1];
-    // the key's chunk sums are contiguous; eight at a time, loads in flight together, the
+    // the key's chunk sums are contiguous; sixteen at a time, loads in flight together, the
     // additions in chunk order
-    for (int t = t0; t < t1; t += 8) {
-      C x[8];
+    constexpr int FB = 16;
+    for (int t = t0; t < t1; t += FB) {
+      C x[FB];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) x[q] = pr[(int64_t)min(t + q, t1 - 1) * 16];
+      for (int q = 0; q < FB; ++q) x[q] = pr[(int64_t)min(t + q, t1 - 1) * 16];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
+      for (int q = 0; q < FB; ++q)
         if (t + q < t1) sum += x[q];
     }
     gs[wv][sg][k] = sum;
