@@ -720,14 +720,13 @@ struct UpdArgs {
 // points x 4 projectors] (the grouped table) times K [4 projectors x 16 columns] (4 runs x
 // primal/dual x re/im), accumulated over the keys with MFMA 16x16x4 in four 16-point row
 // blocks.  One vector load brings a key's K operand for all four runs; keys go in
-// batches (two in FP64, four in FP32 arithmetic) whose loads are issued while the
-// previous batch is on the matrix cores.  The 64 x 16 result goes through LDS to lane =
-// point for the update of r.
+// batches of four whose loads are issued while the previous batch is on the matrix cores.
+// The 64 x 16 result goes through LDS to lane = point for the update of r.
 constexpr int UR = 4;
 
 template <typename R, typename C>
 __global__ void __launch_bounds__(256) k_update(UpdArgs<R> a) {
-  constexpr int KB = sizeof(C) == 8 ? 2 : 4;   // keys per batch
+  constexpr int KB = 4;   // keys per batch
   __shared__ double red[4][UR][4];
   __shared__ C tile[4][KG][17];
   const int nslots = (a.list != nullptr) ? *a.count : a.nruns;

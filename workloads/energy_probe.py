@@ -4,7 +4,7 @@ number of iterations, and the relative residual it reaches; plus the conventiona
 H(k) at real k, whose crossings with E count the propagating modes (a lower bound on the
 eigenvalues in the annulus).
 
-    python -m workloads.energy_probe --config 5 --energies -0.6,-0.5,-0.4 --iters 3000
+    python -m workloads.energy_probe --config 5 --energies=-0.6,-0.5,-0.4 --iters 3000
 
 Runs on the GPU through the library (one MI355X); prints one line per energy.
 """
