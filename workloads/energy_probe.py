@@ -38,9 +38,15 @@ def main():
     eps = None
     if a.bands > 0:
         ks = np.linspace(0.0, np.pi / cl, a.nk)
-        eps, res, _, _, rc = s.bands(ks, a.bands, tol=1e-9)
+        rows = []
+        for k in ks:   # one k at a time, so a long band computation reports as it goes
+            e, _, _, it, rc = s.bands(np.array([k]), a.bands, tol=1e-9)
+            rows.append(e[0])
+            print(f"#   k = {k:.5f}: bands {e[0, 0]:.4f} .. {e[0, -1]:.4f} Ha ({it[0]} filter steps, rc {rc})",
+                  flush=True)
+        eps = np.array(rows)
         print(f"# {sysw.name}: N = {sysw.n}, {a.bands} bands of H(k) at {a.nk} k in [0, pi/a]: lowest "
-              f"{eps.min():.4f} Ha, top of the band set {eps[:, -1].min():.4f} Ha (rc {rc}); crossings are "
+              f"{eps.min():.4f} Ha, top of the band set {eps[:, -1].min():.4f} Ha; crossings are "
               f"counted only below that top", flush=True)
     for E in (float(x) for x in a.energies.split(",")):
         prm = cbs.default_params(precision=0, max_iter=a.iters)
