@@ -371,10 +371,7 @@ __global__ void __launch_bounds__(BT_MAXP * RG, 4) k_bra_tile(BraTileArgs<R, C> 
     any = run >= 0;
   }
   if (!__syncthreads_or(any)) return;
-  // primal and dual halves in two planes of 16-byte (8-byte in complex64) elements: the
-  // random point reads of a wave's pieces then spread over twice as many bank offsets
-  cplx<R>* vsa = reinterpret_cast<cplx<R>*>(lds);
-  cplx<R>* vsb = vsa + RG * (TP + 1);
+  Pair<R>* vs = reinterpret_cast<Pair<R>*>(lds);
   const int64_t p0 = (int64_t)c * TP;
   const int np = (int)min<int64_t>(TP, a.N - p0);
   const int j = tid % RG, lp = tid / RG;
@@ -409,13 +406,11 @@ __global__ void __launch_bounds__(BT_MAXP * RG, 4) k_bra_tile(BraTileArgs<R, C> 
     for (int q = 0; q < SPT; ++q) {
       const int i = tid + q * NT;
       const int jj = i / TP, pt = i - jj * TP;
-      vsa[jj * (TP + 1) + pt] = tmp[q].a;
-      vsb[jj * (TP + 1) + pt] = tmp[q].b;
+      vs[jj * (TP + 1) + pt] = tmp[q];
     }
   }
   __syncthreads();
-  const cplx<R>* vja = vsa + j * (TP + 1);
-  const cplx<R>* vjb = vsb + j * (TP + 1);
+  const Pair<R>* vj = vs + j * (TP + 1);
   C acc[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) acc[k] = 0;
@@ -430,9 +425,7 @@ __global__ void __launch_bounds__(BT_MAXP * RG, 4) k_bra_tile(BraTileArgs<R, C> 
       }
 #pragma unroll
       for (int q = 0; q < EB; ++q) {
-        Pair<R> x;
-        x.a = vja[pts[q]];
-        x.b = vjb[pts[q]];
+        const Pair<R> x = vj[pts[q]];
         const C u4[4] = {(C)us[q].x, (C)us[q].y, (C)us[q].z, (C)us[q].w};
         const C xs[4] = {(C)x.a.x, (C)x.a.y, (C)x.b.x, (C)x.b.y};
 #pragma unroll
