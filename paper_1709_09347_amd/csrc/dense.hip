@@ -8,6 +8,7 @@
 // Small matrices are column-major: element (i, j) at a[i + j*lda].
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -770,6 +771,7 @@ int32_t svd(int32_t n, c64* A, int32_t lda, c64* V, int32_t ldv, double* sigma, 
   } fr{flag};
   hipLaunchKernelGGL(k_svd_init, dim3(std::min(1024, (n * n + 255) / 256)), dim3(256), 0, st, n, V, ldv, flag);
   CBS_HIP(hipGetLastError());
+  int sweeps = 0;
   for (int sweep = 0; sweep < 60; ++sweep) {
     for (int r = 0; r < nb - 1; ++r) {
       hipLaunchKernelGGL(k_svd_block, dim3(nb / 2), dim3(BJ_THREADS), 0, st, n, bs, nb, r, A, lda, V, ldv, flag);
@@ -780,9 +782,12 @@ int32_t svd(int32_t n, c64* A, int32_t lda, c64* V, int32_t ldv, double* sigma, 
     CBS_HIP(hipStreamSynchronize(st));
     double om = 0;
     std::memcpy(&om, &h, sizeof(om));
+    sweeps = sweep + 1;
     if (!(om >= 1e-13)) break;   // converged (or nothing rotated)
     CBS_HIP(hipMemsetAsync(flag, 0, sizeof(unsigned long long), st));
   }
+  if (const char* v = getenv("CBS_VERBOSE"))
+    if (v[0] == '3') fprintf(stderr, "[cbs] svd: order %d, %d blocks of %d, %d sweeps\n", n, nb, bs, sweeps);
   hipLaunchKernelGGL(k_svd_finish, dim3(1), dim3(JWG), 0, st, n, A, lda, sigma, perm);
   CBS_HIP(hipGetLastError());
   return CBS_OK;
