@@ -281,6 +281,7 @@ struct cbs_system {
   int32_t bra_spread[2] = {1, 1};   // 1: consecutive bra workgroups on different XCDs (same runs)
   int32_t bra_tile[2] = {0, 0};     // full-batch bra: 0 = per atom (MFMA), else runs per chunked workgroup
   int32_t bra_tp[2] = {1, 1};       // chunked bra: which chunk length (index into BT_TPS)
+  int32_t bra_qx[2] = {0, 0};       // chunked bra: table loads per lane (0) or shared by quads (1)
   int32_t upd_pts = 2048;           // points per chunk of the residual update (its partial sums)
   int32_t tuned = 0;                // tile heights picked by the autotuner
   int64_t solve_id = 0;             // stored solves so far (see cbs_system_solve_id)

@@ -333,11 +333,48 @@ struct BraTileArgs {
   C* part;   // [run][slot in key order][16]: u_i times (primal re, primal im, dual re, dual im), i major
 };
 
+// Value of lane I of this lane's quad (quad_perm DPP: every lane of the quad reads lane I).
+template <int I>
+__device__ __forceinline__ int quad_pick(int v) {
+  return __builtin_amdgcn_mov_dpp(v, I * 0x55, 0xF, 0xF, true);
+}
+template <int I>
+__device__ __forceinline__ float quad_pick(float v) {
+  return __int_as_float(quad_pick<I>(__float_as_int(v)));
+}
+template <int I>
+__device__ __forceinline__ double quad_pick(double v) {
+  return __hiloint2double(quad_pick<I>(__double2hiint(v)), quad_pick<I>(__double2loint(v)));
+}
+
+// Entry Q of a group of four consecutive entries, whose point and projector values lane Q of
+// the quad loaded: the sixteen products with this lane's run, added in entry order.
+template <int Q, typename R, typename C, typename U4>
+__device__ __forceinline__ void bt_entry(C (&acc)[16], const Pair<R>* vj, int ptm, const U4& um) {
+  const Pair<R> x = vj[quad_pick<Q>(ptm)];
+  const C u4[4] = {(C)quad_pick<Q>(um.x), (C)quad_pick<Q>(um.y), (C)quad_pick<Q>(um.z), (C)quad_pick<Q>(um.w)};
+  const C xs[4] = {(C)x.a.x, (C)x.a.y, (C)x.b.x, (C)x.b.y};
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[4 * i + k] += u4[i] * xs[k];
+}
+template <typename R, typename C, typename U4>
+__device__ __forceinline__ void bt_group(C (&acc)[16], const Pair<R>* vj, int ptm, const U4& um) {
+  bt_entry<0, R, C, U4>(acc, vj, ptm, um);
+  bt_entry<1, R, C, U4>(acc, vj, ptm, um);
+  bt_entry<2, R, C, U4>(acc, vj, ptm, um);
+  bt_entry<3, R, C, U4>(acc, vj, ptm, um);
+}
+
 // BT_MAXP x RG threads: thread t takes piece t / RG of the chunk (at most BT_MAXP) for run
 // t % RG of the group, so the RG threads of a piece read the same table entries.  The
 // piece's bounds are requested before the staging barrier, so their latency overlaps the
-// staging loads.
-template <typename R, typename C, int RG, int TP>
+// staging loads.  QX = 0: every thread loads each entry of its piece itself; QX = 1: the
+// four lanes of a quad (one piece, RG a multiple of 4) load one entry each of a group of
+// four and pass them round by DPP (a quarter of the table traffic and registers), the next
+// group requested while the current one is used.  Both add the products in the same order.
+template <typename R, typename C, int RG, int TP, int QX>
 __global__ void __launch_bounds__(BT_MAXP * RG, 4) k_bra_tile(BraTileArgs<R, C> a) {
   static_assert(BT_MAXP * RG <= 1024, "one piece per thread row");
   // the staged directions (rows padded by one point against bank conflicts between the
@@ -379,7 +416,9 @@ __global__ void __launch_bounds__(BT_MAXP * RG, 4) k_bra_tile(BraTileArgs<R, C> 
   // this thread's piece
   const int pb = a.piece_off[c];
   const int npc = a.piece_off[c + 1] - pb;
-  const bool work = lp < npc && run >= 0;
+  // with the quad exchange the lanes of a piece walk it together, also for an empty run slot
+  // (staged from run 0's row, its sums never stored)
+  const bool work = lp < npc && (QX > 0 || run >= 0);
   int beg = 0, end = 1;
   if (work) {
     beg = a.piece_beg[pb + lp];
@@ -414,7 +453,21 @@ __global__ void __launch_bounds__(BT_MAXP * RG, 4) k_bra_tile(BraTileArgs<R, C> 
   C acc[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) acc[k] = 0;
-  if (work) {
+  static_assert(QX == 0 || (EB == 4 && RG % 4 == 0), "quad exchange: groups of four entries, quads of one piece");
+  if (QX == 1 && work) {
+    const int ql = tid & 3;
+    int pn = a.ent_pt[beg + ql];
+    U4 un = ut[beg + ql];
+    for (int e0 = beg; e0 < end; e0 += 4) {
+      const int pc = pn;
+      const U4 uc = un;
+      if (e0 + 4 < end) {
+        pn = a.ent_pt[e0 + 4 + ql];
+        un = ut[e0 + 4 + ql];
+      }
+      bt_group<R, C, U4>(acc, vj, pc, uc);
+    }
+  } else if (QX == 0 && work) {
     for (int e0 = beg; e0 < end; e0 += EB) {
       int pts[EB];
       U4 us[EB];
@@ -549,12 +602,20 @@ size_t bra_tile_part_bytes(const cbs_system* s, int32_t nruns) {
   return (size_t)std::max(nruns, 0) * (size_t)ns * 16 * sizeof(double);
 }
 
-template <typename R, typename C, int RG>
-static void launch_tile_tp(int tp, int grid, hipStream_t st, const BraTileArgs<R, C>& t) {
+template <typename R, typename C, int RG, int QX>
+static void launch_tile_qx(int tp, int grid, hipStream_t st, const BraTileArgs<R, C>& t) {
   if (tp == 256)
-    hipLaunchKernelGGL((k_bra_tile<R, C, RG, 256>), dim3(grid), dim3(BT_MAXP * RG), 0, st, t);
+    hipLaunchKernelGGL((k_bra_tile<R, C, RG, 256, QX>), dim3(grid), dim3(BT_MAXP * RG), 0, st, t);
   else
-    hipLaunchKernelGGL((k_bra_tile<R, C, RG, 512>), dim3(grid), dim3(BT_MAXP * RG), 0, st, t);
+    hipLaunchKernelGGL((k_bra_tile<R, C, RG, 512, QX>), dim3(grid), dim3(BT_MAXP * RG), 0, st, t);
+}
+
+template <typename R, typename C, int RG>
+static void launch_tile_tp(int tp, int qx, int grid, hipStream_t st, const BraTileArgs<R, C>& t) {
+  switch (qx) {
+    case 1: launch_tile_qx<R, C, RG, 1>(tp, grid, st, t); break;
+    default: launch_tile_qx<R, C, RG, 0>(tp, grid, st, t); break;
+  }
 }
 
 template <typename R, typename C>
@@ -588,10 +649,11 @@ static int32_t launch_bra_tile(const cbs_system* s, const ChunkTables& d, int rg
   t.count = count;
   t.part = (C*)part;
   const int grid = (t.nlogical + 7) / 8 * 8;
+  const int qx = s->bra_qx[std::is_same<R, float>::value ? 1 : 0];
   if (rg == 4)
-    launch_tile_tp<R, C, 4>(d.tp, grid, st, t);
+    launch_tile_tp<R, C, 4>(d.tp, qx, grid, st, t);
   else if (rg == 8)
-    launch_tile_tp<R, C, 8>(d.tp, grid, st, t);
+    launch_tile_tp<R, C, 8>(d.tp, qx, grid, st, t);
   else {
     set_error("chunked bra: %d runs per workgroup unsupported", rg);
     return CBS_EINVAL;

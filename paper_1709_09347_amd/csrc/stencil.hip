@@ -552,7 +552,7 @@ static int32_t tune_nonlocal(cbs_system* s, hipStream_t st, bool tune_update, st
   s->bra_nw[pi] = bnw;
   s->bra_spread[pi] = bsp;
   // the chunked bra with 4, 8 (and in complex64 16) runs per workgroup, for each chunk length
-  int btile = 0, btp = 1;
+  int btile = 0, btp = 1, bqx = 0;
   const size_t bpart_bytes = bra_tile_part_bytes(s, nr);
   if (bpart_bytes > 0) {
     unsigned char* bpart = nullptr;
@@ -560,29 +560,34 @@ static int32_t tune_nonlocal(cbs_system* s, hipStream_t st, bool tune_update, st
     for (int ti = 0; ti < 2; ++ti) {
       if (s->proj.bt[ti].nslots == 0) continue;
       s->bra_tp[pi] = ti;
-      for (int rg : {4, 8}) {
-        s->bra_tile[pi] = rg;
-        CBS_TRY(launch_bra<R>(s, nr, buf, coef, status, 0, kt, dsc + nr, st, true, nullptr, nullptr, false, bpart));
-        CBS_HIP(hipEventRecord(e0, st));
-        for (int k = 0; k < 3; ++k)
+      for (int rg : {4, 8})
+        for (int qx : {0, 1}) {
+          s->bra_tile[pi] = rg;
+          s->bra_qx[pi] = qx;
           CBS_TRY(launch_bra<R>(s, nr, buf, coef, status, 0, kt, dsc + nr, st, true, nullptr, nullptr, false, bpart));
-        CBS_HIP(hipEventRecord(e1, st));
-        CBS_HIP(hipEventSynchronize(e1));
-        float ms = 0;
-        CBS_HIP(hipEventElapsedTime(&ms, e0, e1));
-        char line[96];
-        snprintf(line, sizeof(line), "%s chunked bra %d runs x %d points %.4f ms; ", tag, rg, BT_TPS[ti], ms / 3);
-        log += line;
-        if (ms < best) {
-          best = ms;
-          btile = rg;
-          btp = ti;
+          CBS_HIP(hipEventRecord(e0, st));
+          for (int k = 0; k < 3; ++k)
+            CBS_TRY(launch_bra<R>(s, nr, buf, coef, status, 0, kt, dsc + nr, st, true, nullptr, nullptr, false, bpart));
+          CBS_HIP(hipEventRecord(e1, st));
+          CBS_HIP(hipEventSynchronize(e1));
+          float ms = 0;
+          CBS_HIP(hipEventElapsedTime(&ms, e0, e1));
+          char line[128];
+          snprintf(line, sizeof(line), "%s chunked bra %d runs x %d points qx %d %.4f ms; ", tag, rg, BT_TPS[ti],
+                   qx, ms / 3);
+          log += line;
+          if (ms < best) {
+            best = ms;
+            btile = rg;
+            btp = ti;
+            bqx = qx;
+          }
         }
-      }
     }
   }
   s->bra_tile[pi] = btile;
   s->bra_tp[pi] = btp;
+  s->bra_qx[pi] = bqx;
   if (tune_update) {
     best = 1e30f;
     int bpts = 2048;
@@ -610,9 +615,10 @@ static int32_t tune_nonlocal(cbs_system* s, hipStream_t st, bool tune_update, st
   return CBS_OK;
 }
 
-// CBS_BRA_TILE=<runs>[:<points>] fixes the full-batch bra after tuning: runs 0 = per atom,
-// 4 or 8 = chunked with that many runs per workgroup, on chunks of 256 or 512 points
-// (default 512); CBS_BRA_NW (4 or 8) and CBS_BRA_SPREAD (0 or 1) fix the per-atom bra's
+// CBS_BRA_TILE=<runs>[:<points>[:<qx>]] fixes the full-batch bra after tuning: runs 0 = per
+// atom, 4 or 8 = chunked with that many runs per workgroup, on chunks of 256 or 512 points
+// (default 512), with table loads per lane (qx 0, the default) or shared by quads (1, see
+// k_bra_tile); CBS_BRA_NW (4 or 8) and CBS_BRA_SPREAD (0 or 1) fix the per-atom bra's
 // waves and workgroup order.
 static int32_t bra_override(cbs_system* s) {
   if (const char* w = getenv("CBS_BRA_NW")) s->bra_nw[0] = s->bra_nw[1] = atoi(w) == 8 ? 8 : 4;
@@ -622,14 +628,17 @@ static int32_t bra_override(cbs_system* s) {
   const int rg = atoi(e);
   const char* colon = strchr(e, ':');
   const int tp = colon ? atoi(colon + 1) : 512;
-  if ((rg != 0 && rg != 4 && rg != 8) || (tp != 256 && tp != 512)) {
-    set_error("CBS_BRA_TILE=%s: expected 0, 4 or 8 runs, optionally :256 or :512 points", e);
+  const char* colon2 = colon ? strchr(colon + 1, ':') : nullptr;
+  const int qx = colon2 ? atoi(colon2 + 1) : 0;
+  if ((rg != 0 && rg != 4 && rg != 8) || (tp != 256 && tp != 512) || qx < 0 || qx > 1) {
+    set_error("CBS_BRA_TILE=%s: expected 0, 4 or 8 runs, optionally :256 or :512 points and :0 or :1", e);
     return CBS_EINVAL;
   }
   const int ti = tp == 256 ? 0 : 1;
   if (rg > 0 && s->proj.bt[ti].nslots == 0) return CBS_OK;   // no chunked tables for this cell
   s->bra_tile[0] = s->bra_tile[1] = rg;
   s->bra_tp[0] = s->bra_tp[1] = ti;
+  s->bra_qx[0] = s->bra_qx[1] = qx;
   return CBS_OK;
 }
 

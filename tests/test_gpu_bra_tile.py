@@ -4,12 +4,15 @@ and the per-atom bra (paper Sec. 4: separable nonlocal projectors; Sec. 3.2: BiC
 
 The bra sits inside the operator, so the tests pick it with CBS_BRA_TILE (read when a
 system is first tuned: 0 = per atom, 4 / 8 = chunked with that many runs per
-workgroup, on chunks of 512 points or, with ":256", of 256) and check what BiCG and the solve return.  Bars: on the 5x5x8 cell every
+workgroup, on chunks of 512 points or, with ":256", of 256; a third field for the
+table loads: 0 per lane, 1 shared by the four lanes of a quad) and check what BiCG and the
+solve return.  Bars: on the 5x5x8 cell every
 solution's residual, recomputed by the oracle, <= 1e-10 and the solution within 1e-8 of LU;
 at 48x48x32 (full size) BiCG capped at 20 iterations against the oracle's BiCG after the
 same 20 steps on its sparse operator, iterates to 1e-10 relative (the same recurrences:
-only the order in which the bra adds separates them); the full mixed-precision solve with
-the chunked bra against the per-atom bra, eigenvalues to 1e-9 relative.
+only the order in which the bra adds separates them); the two table-load modes, which add
+in the same order, bit for bit against each other; the full mixed-precision solve with the
+chunked bra against the per-atom bra, eigenvalues to 1e-9 relative.
 """
 import numpy as np
 import pytest
@@ -27,7 +30,7 @@ def _system(monkeypatch, sysw, rg):
     return cbs.System.from_workload(sysw)
 
 
-@pytest.mark.parametrize("rg", ["4", "8", "4:256", "8:256"])
+@pytest.mark.parametrize("rg", ["4", "8", "4:256", "8:256", "4:512:1", "4:256:1", "8:512:1", "8:256:1"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_chunked_bra_tiny_vs_lu(cuda, monkeypatch, rg, precision):
     import torch
@@ -53,7 +56,7 @@ def test_chunked_bra_tiny_vs_lu(cuda, monkeypatch, rg, precision):
             assert np.linalg.norm(Y[j, l] - ref) <= 1e-8 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("rg", ["4", "8", "4:256", "8:256"])
+@pytest.mark.parametrize("rg", ["4", "8", "4:256", "8:256", "4:512:1", "8:512:1"])
 def test_chunked_bra_cfg2_iterates_match_the_oracle(cuda, monkeypatch, rg):
     import torch
     import paper_1709_09347_amd as cbs
@@ -75,6 +78,35 @@ def test_chunked_bra_cfg2_iterates_match_the_oracle(cuda, monkeypatch, rg):
         assert np.linalg.norm(Y[0, l] - x) <= 1e-10 * np.linalg.norm(x)
         assert np.linalg.norm(Yt[0, l] - xt) <= 1e-10 * np.linalg.norm(xt)
         assert abs(relres[0, l, 0] - rr) <= 1e-8 * rr and abs(relres[0, l, 1] - rrt) <= 1e-8 * rrt
+
+
+@pytest.mark.parametrize("tile", ["4:512", "8:512", "4:256"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_chunked_bra_table_load_modes_agree_bit_for_bit(cuda, monkeypatch, tile, precision):
+    """Three right-hand sides at one node: 3 runs, so the last quad of every group of 4 (or 8)
+    runs holds empty run slots, which walk their piece with the others.  In mixed precision
+    the runs narrow to complex64 after a few iterations (inner_tol 0.5), so the complex64
+    bra is compared too."""
+    import torch
+    import paper_1709_09347_amd as cbs
+    w = W.config(2)
+    sysw = w.systems[0]
+    E = w.solve.energies[0]
+    z1, _, _, _ = ss.quadrature(0.5, 32)
+    V = torch.from_numpy(W.make_rhs(sysw.n, 3, 11)).to(cuda)
+    prm = cbs.default_params(precision=precision, max_iter=30)
+    prm.inner_tol = 0.5
+    out = {}
+    modes = ("0", "1")
+    for mode in modes:
+        s = _system(monkeypatch, sysw, f"{tile}:{mode}")
+        Y, Yt, iters, relres, info, rc = s.bicg(E, z1[[5]], V, prm)
+        assert rc == cbs.CBS_ENOCONV and iters.min() == 30
+        out[mode] = (Y.cpu().numpy(), Yt.cpu().numpy(), relres.copy())
+        del s
+    for mode in modes[1:]:
+        for a, b in zip(out[modes[0]], out[mode]):
+            assert np.array_equal(a, b), f"table-load mode {mode} differs from mode {modes[0]}"
 
 
 def test_chunked_bra_cfg2_mixed_solve_matches_the_per_atom_bra(cuda, monkeypatch):
