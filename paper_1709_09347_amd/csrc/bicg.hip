@@ -368,6 +368,7 @@ __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t 
     const double vn = sc.vn2[run];
     sc.relres[2 * run] = zero ? 0.0 : (vn > 0 ? sqrt(s[2] / vn) : 1.0);
     sc.relres[2 * run + 1] = zero ? 0.0 : (vn > 0 ? sqrt(s[3] / vn) : 1.0);
+    sc.rmin[run] = fmax(sc.relres[2 * run], sc.relres[2 * run + 1]);
     sc.status[run] = zero ? ST_DONE : start;
   }
   __syncthreads();
@@ -453,7 +454,13 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
   sc.rho_prev[run] = ro;
   sc.rho[run] = rn;
   const bool stalled = (st == ST_ACT_LO) && (it - sc.ru_it[run] >= lo_window);
-  if (conv || bad || it >= max_iter || fmax(rr, rrt) < sc.ru_thr[run] || stalled) {
+  // a residual 1e6 times above the smallest since the last replacement: BiCG is diverging
+  // (near a breakdown); the replacement restarts the run from its accumulated solution
+  const double cur = fmax(rr, rrt);
+  const double mn = fmin(sc.rmin[run], cur);
+  sc.rmin[run] = mn;
+  const bool diverged = cur > 1e6 * mn;
+  if (conv || bad || it >= max_iter || cur < sc.ru_thr[run] || stalled || diverged) {
     sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
   } else if (st == ST_ACT_HI && narrow_tol > 0.0 && sc.ru_thr[run] >= 0.0 && fmax(rr, rrt) < narrow_tol) {
     // the residual is small enough for complex64 vectors and operator applications
@@ -497,6 +504,7 @@ __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t 
       const int nru = sc.nru[run] + 1;
       sc.nru[run] = nru;
       sc.ru_it[run] = sc.iters[run];
+      sc.rmin[run] = fmax(rr, rrt);
       sc.xcoef[run] = make_double2(0, 0);
       const double2 rn = make_double2(s[0], s[1]);
       if (rr < tol && rrt < tol) {
@@ -525,6 +533,17 @@ __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t 
           sc.ru_thr[run] = tr * ru_factor;
         } else {
           st = ST_ACT_HI;
+          if (tr > 100.0 * tol) {
+            // a complex128 run is replaced once its recursive residual is below tol, or when
+            // it diverges (k_s2); a true residual far above tol means the recurrence lost its
+            // accuracy (a near-breakdown made the iterate a sum of large, cancelling terms):
+            // restart BiCG from the accumulated solution, the true residual as the first
+            // search direction, instead of continuing recurrences whose scalars no longer
+            // match the residual (in mixed mode k_phase also clears the old direction)
+            sc.beta[run] = make_double2(0, 0);
+            sc.conv[run] = 1;
+            sc.nrestart[run] += 1;
+          }
           sc.ru_thr[run] = (sc.ru_thr[run] < 0.0) ? -1.0 : 0.0;
         }
       }
@@ -739,6 +758,7 @@ __global__ void __launch_bounds__(256) k_q_s0(BicgScal sc, QueueState q, int32_t
     const bool zero = s[2] == 0.0 && s[3] == 0.0;
     sc.relres[2 * run] = zero ? 0.0 : 1.0;
     sc.relres[2 * run + 1] = zero ? 0.0 : 1.0;
+    sc.rmin[run] = 1.0;
     sc.status[run] = zero ? ST_DONE : ST_ACT_HI;
   }
   __syncthreads();
@@ -861,6 +881,7 @@ int32_t bicg_alloc(BicgSolve& b, const char* tag) {
   CBS_TRY(ws_get(ws, (t + ".vn2").c_str(), R, &b.sc.vn2));
   CBS_TRY(ws_get(ws, (t + ".relres").c_str(), 2 * R, &b.sc.relres));
   CBS_TRY(ws_get(ws, (t + ".ruthr").c_str(), R, &b.sc.ru_thr));
+  CBS_TRY(ws_get(ws, (t + ".rmin").c_str(), R, &b.sc.rmin));
   CBS_TRY(ws_get(ws, (t + ".status").c_str(), R, &b.sc.status));
   CBS_TRY(ws_get(ws, (t + ".iters").c_str(), R, &b.sc.iters));
   CBS_TRY(ws_get(ws, (t + ".brk").c_str(), R, &b.sc.brk));

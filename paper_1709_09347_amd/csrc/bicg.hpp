@@ -31,6 +31,7 @@ struct BicgScal {
   double* vn2;        // ||v||^2 of the run's right-hand side
   double* relres;     // [2*run]: primal, dual relative residual (last known)
   double* ru_thr;     // complex64 phase: next replacement below this; -1: kept in complex128
+  double* rmin;       // smallest max(primal, dual) residual since the last replacement
   int32_t* status;
   int32_t* iters;
   int32_t* brk;

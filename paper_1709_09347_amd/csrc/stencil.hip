@@ -56,6 +56,15 @@ __device__ __forceinline__ double2 wave_sum2(double2 v) {
   return v;
 }
 
+// The direction p = r + beta p_old, with the roundings fixed by explicit fused multiply-adds:
+// the halo planes recompute what the tile that owns them stored, and the two must agree bit
+// for bit (the operator is applied to the stored direction), whatever the compiler would
+// contract in either place.
+template <typename C>
+__device__ __forceinline__ cplx<C> dir_fma(cplx<C> r, cplx<C> b, cplx<C> p) {
+  return mkc<C>(fma(-b.y, p.y, fma(b.x, p.x, r.x)), fma(b.y, p.x, fma(b.x, p.y, r.y)));
+}
+
 // R: storage precision of the vectors (and of the LDS plane); C: arithmetic precision.
 template <typename R, typename C, int P, bool BICG>
 __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
@@ -166,8 +175,8 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
         const int64_t n = base + xx + (int64_t)nx * gy + plane * mm;
         Pair<C> v = pcast<C, R>(pr_r[k]);
         const Pair<C> po = pcast<C, R>(pr_p[k]);
-        v.a = cfma<C>(v.a, ba, po.a);
-        v.b = cfma<C>(v.b, bb, po.b);
+        v.a = dir_fma<C>(v.a, ba, po.a);
+        v.b = dir_fma<C>(v.b, bb, po.b);
         const Pair<R> vs = pcast<R, C>(v);
         if (r >= P && r < P + TY && uy < ny) {
           a.pnew[n] = vs;
@@ -210,8 +219,8 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
         if (BICG) {
           Pair<C> v = pcast<C, R>(a.rin[n]);
           const Pair<C> po = pcast<C, R>(a.pold[n]);
-          v.a = cfma<C>(v.a, ba, po.a);
-          v.b = cfma<C>(v.b, bb, po.b);
+          v.a = dir_fma<C>(v.a, ba, po.a);
+          v.b = dir_fma<C>(v.b, bb, po.b);
           const Pair<R> vs = pcast<R, C>(v);   // the stored direction is the one applied
           if (r >= P && r < P + TY && uy < ny) {
             a.pnew[n] = vs;
@@ -270,8 +279,8 @@ __global__ void __launch_bounds__(512) k_stencil(StArgs<R> a) {
       Pair<C> v = pcast<C, R>(a.rin[n]);
       if (BICG) {
         const Pair<C> po = pcast<C, R>(a.pold[n]);
-        v.a = cfma<C>(v.a, ba, po.a);
-        v.b = cfma<C>(v.b, bb, po.b);
+        v.a = dir_fma<C>(v.a, ba, po.a);
+        v.b = dir_fma<C>(v.b, bb, po.b);
         v = pcast<C, R>(pcast<R, C>(v));   // as stored by the tile that owns the plane
       }
       if (m < 0) {

@@ -76,6 +76,31 @@ def test_bicg_cfg2_full_size_sampled(cuda, precision):
             assert np.linalg.norm(V[l] - H.apply(z2[j], Yt[j, l], E)) / nv <= 1e-10
 
 
+def test_bicg_cfg1_every_run_reaches_1e12(cuda):
+    """Every node and right-hand side of cfg1 at E = 0.3 to 1e-12 (near BiCG's attainable
+    accuracy there): a run whose residual diverges, or whose recursive residual drifts far
+    from the true one, restarts from its accumulated solution instead of iterating to the
+    cap; every solution's residual, recomputed by the oracle, within 1e-11."""
+    import torch
+    import paper_1709_09347_amd as cbs
+    sysw = W.config(1).systems[0]
+    H = ham.build(sysw)
+    E = 0.3
+    z1, _, z2, _ = ss.quadrature(0.5, 32)
+    V = W.make_rhs(sysw.n, 8, 3)
+    s = cbs.System.from_workload(sysw)
+    Y, Yt, iters, relres, info, rc = s.bicg(E, z1, torch.from_numpy(V).to(cuda),
+                                            cbs.default_params(precision=0, max_iter=3000, tol=1e-12))
+    print(f"iterations max {iters.max()} mean {iters.mean():.1f}")
+    assert rc == 0 and iters.max() < 3000 and relres.max() <= 1e-12
+    Y, Yt = Y.cpu().numpy(), Yt.cpu().numpy()
+    worst = np.unravel_index(np.argsort(iters, axis=None)[-4:], iters.shape)
+    for j, l in zip(*worst):
+        nv = np.linalg.norm(V[l])
+        assert np.linalg.norm(V[l] - H.apply(z1[j], Y[j, l], E)) / nv <= 1e-11
+        assert np.linalg.norm(V[l] - H.apply(z2[j], Yt[j, l], E)) / nv <= 1e-11
+
+
 def test_bicg_max_iter_reports_noconv(cuda):
     import torch
     import paper_1709_09347_amd as cbs
