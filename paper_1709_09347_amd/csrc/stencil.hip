@@ -501,10 +501,11 @@ static int32_t tune_one(cbs_system* s, hipStream_t st, int32_t* best_ty, std::st
   return CBS_OK;
 }
 
-// Times the full-batch projector bra for 4 or 8 waves per (atom, 16 runs) and for the two
-// block orders (consecutive workgroups on one XCD or spread over the XCDs), and (complex128
-// only) the residual update for 1024, 2048 and 4096 points per chunk; keeps the fastest of
-// each.  Same scratch batch as the stencil tiles.
+// Times the full-batch projector bra: per atom for 4 or 8 waves per (atom, 16 runs) and the
+// two block orders (consecutive workgroups on one XCD or spread over the XCDs), and chunked
+// for 4 or 8 runs per workgroup, chunks of 256 or 512 points and table loads per lane or
+// shared by quads; and (complex128 only) the residual update for 1024, 2048 and 4096 points
+// per chunk.  Keeps the fastest of each.  Same scratch batch as the stencil tiles.
 template <typename R>
 static int32_t tune_nonlocal(cbs_system* s, hipStream_t st, bool tune_update, std::string& log) {
   const int pi = std::is_same<R, float>::value ? 1 : 0;
@@ -560,7 +561,7 @@ static int32_t tune_nonlocal(cbs_system* s, hipStream_t st, bool tune_update, st
     }
   s->bra_nw[pi] = bnw;
   s->bra_spread[pi] = bsp;
-  // the chunked bra with 4, 8 (and in complex64 16) runs per workgroup, for each chunk length
+  // the chunked bra with 4 or 8 runs per workgroup, for each chunk length and table-load mode
   int btile = 0, btp = 1, bqx = 0;
   const size_t bpart_bytes = bra_tile_part_bytes(s, nr);
   if (bpart_bytes > 0) {
