@@ -40,7 +40,7 @@ METRIC = "time per energy to 1e-10 residual (mixed vs FP64 GPU); stencil HBM GB/
 # FETCH_SIZE and WRITE_SIZE on full-batch dispatches of this workload, each scaled by what the
 # counter reads for a plain 1 GiB device copy (bench.py --copy-calibration); the commands and
 # raw figures are in profiles/stencil_fp64_48x48x32_counters.md.  None once the kernel changes.
-STENCIL_TRAFFIC_RATIO = 1.0329
+STENCIL_TRAFFIC_RATIO = 1.1093
 # solve tolerance of the eigenpair-residual leg: the Rayleigh-Ritz pairs carry 10-15x the
 # solve residual at this workload (1.2e-10 from solves to 1e-11), so 5e-12 keeps them
 # below 1e-10
