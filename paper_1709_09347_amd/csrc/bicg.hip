@@ -418,7 +418,8 @@ __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t 
 // decisions.  The list of runs marked for replacement is built afterwards (k_ru_list).
 __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
                                             double tol, int32_t max_iter, double narrow_tol, double ru_factor,
-                                            int32_t lo_window, double* hist, int32_t hstride, int32_t hrows) {
+                                            int32_t lo_window, double div_factor, double* hist, int32_t hstride,
+                                            int32_t hrows) {
   const int lane = threadIdx.x & 63;
   const int run = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (run >= nruns) return;
@@ -454,12 +455,14 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
   sc.rho_prev[run] = ro;
   sc.rho[run] = rn;
   const bool stalled = (st == ST_ACT_LO) && (it - sc.ru_it[run] >= lo_window);
-  // a residual 1e6 times above the smallest since the last replacement: BiCG is diverging
-  // (near a breakdown); the replacement restarts the run from its accumulated solution
+  // a residual div_factor (1e6) times above the smallest since the last replacement, 20
+  // iterations or more after it (a restarted BiCG rises above its starting residual at
+  // first): the run is diverging (near a breakdown); the replacement restarts it from its
+  // accumulated solution
   const double cur = fmax(rr, rrt);
   const double mn = fmin(sc.rmin[run], cur);
   sc.rmin[run] = mn;
-  const bool diverged = cur > 1e6 * mn;
+  const bool diverged = it - sc.ru_it[run] >= 20 && cur > div_factor * mn;
   if (conv || bad || it >= max_iter || cur < sc.ru_thr[run] || stalled || diverged) {
     sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
   } else if (st == ST_ACT_HI && narrow_tol > 0.0 && sc.ru_thr[run] >= 0.0 && fmax(rr, rrt) < narrow_tol) {
@@ -963,7 +966,7 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
                                 b.upd_part, b.nchunks, st, b.sc.list + b.nruns, b.sc.n_active + 1));
   hipLaunchKernelGGL(k_s2, dim3((b.nruns + 3) / 4), dim3(256), 0, st, b.sc, b.nruns, b.nchunks,
                      (const double*)b.upd_part, b.tol, b.max_iter, b.narrow_tol, b.ru_factor, b.lo_window,
-                     b.hist, b.hist_stride, b.hist_rows);
+                     b.div_factor, b.hist, b.hist_stride, b.hist_rows);
   CBS_HIP(hipGetLastError());
   if (b.half_stop && b.n_q > 0) {
     hipLaunchKernelGGL(k_half_stop, dim3(1), dim3(256), 0, st, b.sc, b.nruns / (b.n_q * b.L), b.n_q, b.L);
@@ -1304,6 +1307,13 @@ void configure_solve(BicgSolve& b, const cbs_params* prm) {
   b.max_ru = std::max(prm->max_refine, 1);
   b.half_stop = prm->half_stop;
   b.lo_window = prm->lo_window > 0 ? prm->lo_window : 300;
+  // CBS_DIVERGE_FACTOR overrides the divergence guard's factor (tests set it low to drive the
+  // restart path on ordinary residual bumps)
+  b.div_factor = 1e6;
+  if (const char* e = getenv("CBS_DIVERGE_FACTOR")) {
+    const double f = atof(e);
+    if (f > 1.0) b.div_factor = f;
+  }
 }
 
 __global__ void k_fill_nan(int64_t n, double* p) {

@@ -101,6 +101,7 @@ struct BicgSolve {
   void* bra_part = nullptr;   // chunk sums of the chunked bra (NULL: the per-atom bra)
   BicgScal sc{};
   double tol = 1e-10, ru_factor = 1e-2, narrow_tol = 0.0;
+  double div_factor = 1e6;   // a residual this far above its smallest since the last replacement: diverging
   int32_t max_iter = 10000, max_ru = 1000, half_stop = 0;
   int32_t lo_window = 300;   // complex64 iterations without a 100x drop before a forced replacement
   double* hist = nullptr;    // [hist_rows][nruns][2] recursive relative residuals, NULL: not recorded

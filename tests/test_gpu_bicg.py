@@ -101,6 +101,45 @@ def test_bicg_cfg1_every_run_reaches_1e12(cuda):
         assert np.linalg.norm(V[l] - H.apply(z2[j], Yt[j, l], E)) / nv <= 1e-11
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bicg_restart_path_converges(cuda, monkeypatch, precision):
+    """The near-breakdown restart driven on purpose.  A first solve records the residual
+    histories; BiCG's residual rises well above its running minimum as it goes (40-250x here),
+    far below the guard's default factor of 1e6.  The second solve sets CBS_DIVERGE_FACTOR to half
+    the largest such rise, so at least that run is sent to a replacement and, its true
+    residual being far above tol, restarted from its accumulated solution.  The restarts must
+    happen, and every run still reach tol with solutions whose residuals, recomputed by the
+    oracle, meet it."""
+    import torch
+    import paper_1709_09347_amd as cbs
+    sysw = W.config(1).systems[0]
+    H = ham.build(sysw)
+    E = 0.3
+    z1, _, z2, _ = ss.quadrature(0.5, 32)
+    sel = [0, 10, 16, 31]
+    V = W.make_rhs(sysw.n, 4, 3)
+    Vd = torch.from_numpy(V).to(cuda)
+    s = cbs.System.from_workload(sysw)
+    prm = cbs.default_params(precision=precision, max_iter=20000)
+    out = s.bicg(E, z1[sel], Vd, prm, history=(1, 2000))
+    assert out[5] == 0 and out[4].restarts == 0
+    r = np.asarray(out[6]).reshape(2000, -1, 2).max(axis=2)
+    rise = 1.0
+    for run in range(r.shape[1]):
+        x = r[:, run][r[:, run] > 0]
+        rise = max(rise, float(np.max(x[20:] / np.minimum.accumulate(x)[20:])))
+    monkeypatch.setenv("CBS_DIVERGE_FACTOR", f"{rise / 2:.6g}")
+    Y, Yt, iters, relres, info, rc = s.bicg(E, z1[sel], Vd, prm)
+    print(f"largest rise {rise:.3g}; restarts {info.restarts}, iterations max {iters.max()} mean {iters.mean():.1f}")
+    assert rc == 0 and info.restarts > 0 and relres.max() <= 1e-10
+    Y, Yt = Y.cpu().numpy(), Yt.cpu().numpy()
+    for jj, j in enumerate(sel):
+        for l in range(V.shape[0]):
+            nv = np.linalg.norm(V[l])
+            assert np.linalg.norm(V[l] - H.apply(z1[j], Y[jj, l], E)) / nv <= 1e-10
+            assert np.linalg.norm(V[l] - H.apply(z2[j], Yt[jj, l], E)) / nv <= 1e-10
+
+
 def test_bicg_max_iter_reports_noconv(cuda):
     import torch
     import paper_1709_09347_amd as cbs
