@@ -104,13 +104,16 @@ __global__ void __launch_bounds__(256) k_partials(int64_t N, int32_t nchunks, in
 }
 
 // Residual replacement, first half: x += xcoef p (the pending update), y += x, x = 0.
-// Work items: (entry of the replacement list, chunk of points), taken grid-stride by a
-// bounded grid (the list is short); runs of the other phase are skipped.
+// The run's latest direction p is in the buffer of the iteration that marked it (ru_par);
+// marked on the previous iteration, it is also copied to this iteration's buffer, the one
+// the run's next stencil pass reads as p_old.  Work items: (entry of the replacement list,
+// chunk of points), taken grid-stride by a bounded grid (the list is short); runs of the
+// other phase are skipped.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ru_pre(int64_t N, int32_t nchunks, int32_t nlogical, const int32_t* list,
                                                 const int32_t* count, const int32_t* status, int32_t need,
-                                                const double2* xcoef, const Pair<T>* P, Pair<T>* X,
-                                                Pair<double>* Y) {
+                                                const double2* xcoef, const int32_t* ru_par, int32_t parity,
+                                                Pair<T>* P0, Pair<T>* P1, Pair<T>* X, Pair<double>* Y) {
   const int nl = min(nlogical, *count * nchunks);
   for (int lb = blockIdx.x; lb < nl; lb += gridDim.x) {
     const int slot = lb / nchunks, ch = lb - slot * nchunks;
@@ -120,10 +123,15 @@ __global__ void __launch_bounds__(256) k_ru_pre(int64_t N, int32_t nchunks, int3
     const int64_t lo = ch * chunk, hi = std::min<int64_t>(lo + chunk, N);
     const double2 xc = xcoef[run];
     const cplx<T> xa = mkc<T>((T)xc.x, (T)xc.y), xb = cconj<T>(xa);
+    const int rp = ru_par[run];
+    const Pair<T>* P = rp ? P1 : P0;
+    Pair<T>* Pnow = (parity & 1) ? P1 : P0;
+    const bool copy = rp != (parity & 1);
     for (int64_t n = lo + threadIdx.x; n < hi; n += 256) {
       const int64_t g = (int64_t)run * N + n;
       Pair<T> x = X[g];
       const Pair<T> p = P[g];
+      if (copy) Pnow[g] = p;
       x.a = cfma<T>(x.a, xa, p.a);
       x.b = cfma<T>(x.b, xb, p.b);
       Pair<double> y = Y[g];
@@ -379,7 +387,7 @@ __global__ void __launch_bounds__(256) k_s0(BicgScal sc, int32_t nruns, int32_t 
 // partials of sigma = pt^H q, lane 0 sets alpha.
 __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t n_atoms, const double2* sig_lo,
                                             int32_t nt_lo, const double2* sig_hi, int32_t nt_hi,
-                                            const double2* signl) {
+                                            const double2* signl, int32_t parity) {
   const int lane = threadIdx.x & 63;
   const int run = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (run >= nruns) return;
@@ -405,6 +413,7 @@ __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t 
   if (!(sg.x != 0.0 || sg.y != 0.0) || !finite2(sg)) {
     sc.brk[run] = 1;
     sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
+    sc.ru_par[run] = parity & 1;
     sc.alpha[run] = make_double2(0, 0);
     sc.xcoef[run] = make_double2(0, 0);
     return;
@@ -419,7 +428,7 @@ __global__ void __launch_bounds__(256) k_s1(BicgScal sc, int32_t nruns, int32_t 
 __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t nchunks, const double* part,
                                             double tol, int32_t max_iter, double narrow_tol, double ru_factor,
                                             int32_t lo_window, double div_factor, double* hist, int32_t hstride,
-                                            int32_t hrows) {
+                                            int32_t hrows, int32_t parity) {
   const int lane = threadIdx.x & 63;
   const int run = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (run >= nruns) return;
@@ -465,6 +474,7 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
   const bool diverged = it - sc.ru_it[run] >= 20 && cur > div_factor * mn;
   if (conv || bad || it >= max_iter || cur < sc.ru_thr[run] || stalled || diverged) {
     sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
+    sc.ru_par[run] = parity & 1;
   } else if (st == ST_ACT_HI && narrow_tol > 0.0 && sc.ru_thr[run] >= 0.0 && fmax(rr, rrt) < narrow_tol) {
     // the residual is small enough for complex64 vectors and operator applications
     sc.status[run] = ST_ACT_LO;
@@ -474,7 +484,12 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
   }
 }
 
-__global__ void __launch_bounds__(256) k_ru_list(BicgScal sc, int32_t nruns) { build_ru_list(sc, nruns); }
+// The list of runs marked for replacement, and the active lists without them (the
+// replacement itself runs on odd iterations only; k_s3 rebuilds the lists after it).
+__global__ void __launch_bounds__(256) k_ru_list(BicgScal sc, int32_t nruns) {
+  build_ru_list(sc, nruns);
+  build_lists(sc, nruns);
+}
 
 __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t nchunks, double* part,
                                             double tol, int32_t max_iter, int32_t max_ru, double ru_factor) {
@@ -562,7 +577,8 @@ __global__ void __launch_bounds__(256) k_s3(BicgScal sc, int32_t nruns, int32_t 
 // stop (their iterate is still accumulated by a last replacement).  A run that changes
 // phase this iteration (conv != 0: its complex64 vectors are written only at the end of
 // the iteration) is stopped at the next one.
-__global__ void __launch_bounds__(256) k_half_stop(BicgScal sc, int32_t ngroups, int32_t n_q, int32_t L) {
+__global__ void __launch_bounds__(256) k_half_stop(BicgScal sc, int32_t ngroups, int32_t n_q, int32_t L,
+                                                   int32_t parity) {
   for (int g = threadIdx.x; g < ngroups; g += blockDim.x) {
     int done_nodes = 0;
     for (int j = 0; j < n_q; ++j) {
@@ -575,6 +591,7 @@ __global__ void __launch_bounds__(256) k_half_stop(BicgScal sc, int32_t ngroups,
         const int st = sc.status[r];
         if ((st == ST_ACT_LO || st == ST_ACT_HI) && sc.conv[r] == 0) {
           sc.status[r] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
+          sc.ru_par[r] = parity & 1;
           sc.halt[r] = 1;
         }
       }
@@ -885,6 +902,7 @@ int32_t bicg_alloc(BicgSolve& b, const char* tag) {
   CBS_TRY(ws_get(ws, (t + ".relres").c_str(), 2 * R, &b.sc.relres));
   CBS_TRY(ws_get(ws, (t + ".ruthr").c_str(), R, &b.sc.ru_thr));
   CBS_TRY(ws_get(ws, (t + ".rmin").c_str(), R, &b.sc.rmin));
+  CBS_TRY(ws_get(ws, (t + ".rupar").c_str(), R, &b.sc.ru_par));
   CBS_TRY(ws_get(ws, (t + ".status").c_str(), R, &b.sc.status));
   CBS_TRY(ws_get(ws, (t + ".iters").c_str(), R, &b.sc.iters));
   CBS_TRY(ws_get(ws, (t + ".brk").c_str(), R, &b.sc.brk));
@@ -950,31 +968,12 @@ static int32_t enqueue_stencil_bra(BicgSolve& b, BicgVecs<T>& v, int32_t need, i
   return CBS_OK;
 }
 
-static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
+// Residual replacement of the runs on the list built by k_ru_list: the pending x update and
+// y += x, the true residual v - P(z) y in complex128 (stencil and bra over the short list),
+// and k_s3's decisions.
+static int32_t enqueue_replacement(BicgSolve& b, int parity, hipStream_t st) {
   cbs_system* s = b.sys;
   const int na = s->proj.n_atoms;
-  const int nl = b.nruns * b.nchunks;
-  if (b.mixed) CBS_TRY(enqueue_stencil_bra<float>(b, b.lo, ST_ACT_LO, parity, st));
-  CBS_TRY(enqueue_stencil_bra<double>(b, b.hi, ST_ACT_HI, parity, st));
-  hipLaunchKernelGGL(k_s1, dim3((b.nruns + 3) / 4), dim3(256), 0, st, b.sc, b.nruns, na, (const double2*)b.lo.sig,
-                     b.lo.ntiles, (const double2*)b.hi.sig, b.hi.ntiles, (const double2*)b.signl);
-  CBS_HIP(hipGetLastError());
-  if (b.mixed)
-    CBS_TRY(launch_update<float>(s, b.nruns, b.lo.R, b.lo.Q, b.lo.KT, b.sc.alpha, b.sc.status, ST_ACT_LO,
-                                 b.upd_part, b.nchunks, st, b.sc.list, b.sc.n_active));
-  CBS_TRY(launch_update<double>(s, b.nruns, b.hi.R, b.hi.Q, b.hi.KT, b.sc.alpha, b.sc.status, ST_ACT_HI,
-                                b.upd_part, b.nchunks, st, b.sc.list + b.nruns, b.sc.n_active + 1));
-  hipLaunchKernelGGL(k_s2, dim3((b.nruns + 3) / 4), dim3(256), 0, st, b.sc, b.nruns, b.nchunks,
-                     (const double*)b.upd_part, b.tol, b.max_iter, b.narrow_tol, b.ru_factor, b.lo_window,
-                     b.div_factor, b.hist, b.hist_stride, b.hist_rows);
-  CBS_HIP(hipGetLastError());
-  if (b.half_stop && b.n_q > 0) {
-    hipLaunchKernelGGL(k_half_stop, dim3(1), dim3(256), 0, st, b.sc, b.nruns / (b.n_q * b.L), b.n_q, b.L);
-    CBS_HIP(hipGetLastError());
-  }
-  hipLaunchKernelGGL(k_ru_list, dim3(1), dim3(256), 0, st, b.sc, b.nruns);
-  CBS_HIP(hipGetLastError());
-  // residual replacement of the runs on the list built by k_ru_list
   const int32_t* rul = b.sc.list + 2 * (size_t)b.nruns;
   const int32_t* ruc = b.sc.n_active + 2;
   const int nlr = b.nruns * b.ru_chunks;
@@ -982,10 +981,10 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
   if (b.mixed)
     hipLaunchKernelGGL(k_ru_pre<float>, dim3(gru), dim3(256), 0, st, s->N, b.ru_chunks, nlr, rul, ruc,
                        (const int32_t*)b.sc.status, (int32_t)ST_RU_LO, (const double2*)b.sc.xcoef,
-                       (const Pair<float>*)b.lo.Pb[parity & 1], b.lo.X, b.Y);
+                       (const int32_t*)b.sc.ru_par, parity, b.lo.Pb[0], b.lo.Pb[1], b.lo.X, b.Y);
   hipLaunchKernelGGL(k_ru_pre<double>, dim3(gru), dim3(256), 0, st, s->N, b.ru_chunks, nlr, rul, ruc,
                      (const int32_t*)b.sc.status, (int32_t)ST_RU_HI, (const double2*)b.sc.xcoef,
-                     (const Pair<double>*)b.hi.Pb[parity & 1], b.hi.X, b.Y);
+                     (const int32_t*)b.sc.ru_par, parity, b.hi.Pb[0], b.hi.Pb[1], b.hi.X, b.Y);
   CBS_HIP(hipGetLastError());
   {
     StencilLaunch r{};
@@ -1016,6 +1015,39 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
   hipLaunchKernelGGL(k_s3, dim3(1), dim3(256), 0, st, b.sc, b.nruns, b.ru_chunks, b.ru_part, b.tol,
                      b.max_iter, b.max_ru, b.ru_factor);
   CBS_HIP(hipGetLastError());
+  return CBS_OK;
+}
+
+static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
+  cbs_system* s = b.sys;
+  const int na = s->proj.n_atoms;
+  const int nl = b.nruns * b.nchunks;
+  if (b.mixed) CBS_TRY(enqueue_stencil_bra<float>(b, b.lo, ST_ACT_LO, parity, st));
+  CBS_TRY(enqueue_stencil_bra<double>(b, b.hi, ST_ACT_HI, parity, st));
+  hipLaunchKernelGGL(k_s1, dim3((b.nruns + 3) / 4), dim3(256), 0, st, b.sc, b.nruns, na, (const double2*)b.lo.sig,
+                     b.lo.ntiles, (const double2*)b.hi.sig, b.hi.ntiles, (const double2*)b.signl, parity);
+  CBS_HIP(hipGetLastError());
+  if (b.mixed)
+    CBS_TRY(launch_update<float>(s, b.nruns, b.lo.R, b.lo.Q, b.lo.KT, b.sc.alpha, b.sc.status, ST_ACT_LO,
+                                 b.upd_part, b.nchunks, st, b.sc.list, b.sc.n_active));
+  CBS_TRY(launch_update<double>(s, b.nruns, b.hi.R, b.hi.Q, b.hi.KT, b.sc.alpha, b.sc.status, ST_ACT_HI,
+                                b.upd_part, b.nchunks, st, b.sc.list + b.nruns, b.sc.n_active + 1));
+  hipLaunchKernelGGL(k_s2, dim3((b.nruns + 3) / 4), dim3(256), 0, st, b.sc, b.nruns, b.nchunks,
+                     (const double*)b.upd_part, b.tol, b.max_iter, b.narrow_tol, b.ru_factor, b.lo_window,
+                     b.div_factor, b.hist, b.hist_stride, b.hist_rows, parity);
+  CBS_HIP(hipGetLastError());
+  if (b.half_stop && b.n_q > 0) {
+    hipLaunchKernelGGL(k_half_stop, dim3(1), dim3(256), 0, st, b.sc, b.nruns / (b.n_q * b.L), b.n_q, b.L, parity);
+    CBS_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_ru_list, dim3(1), dim3(256), 0, st, b.sc, b.nruns);
+  CBS_HIP(hipGetLastError());
+  // residual replacement of the runs on the list built by k_ru_list, on odd iterations only
+  // (each of its launches costs a few microseconds even when the list is empty): a run marked
+  // on an even iteration sits out the next one, whose replacement takes it and moves its
+  // direction to that iteration's buffer (k_ru_pre).  Chunks of iterations are even, so
+  // every chunk ends with a replacement.
+  if (parity & 1) CBS_TRY(enqueue_replacement(b, parity, st));
   if (b.mixed) {
     hipLaunchKernelGGL(k_phase, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, (const int32_t*)b.sc.conv,
                        (const Pair<double>*)b.hi.R, b.hi.Pb[parity & 1], b.hi.X, b.lo.R, b.lo.Pb[parity & 1],
@@ -1049,11 +1081,12 @@ static int32_t run_profiled(std::vector<BicgSolve*>& solves, hipStream_t st, int
   }
   int32_t rc = CBS_OK;
   int32_t hna[2];
-  for (int it = 0; it <= max_iter + 1 && rc == CBS_OK; ++it) {
+  for (int it = 0; it <= max_iter + 3 && rc == CBS_OK; ++it) {
     int any = 0;
     for (size_t i = 0; i < solves.size() && rc == CBS_OK; ++i) {
       BicgSolve& b = *solves[i];
-      if (act[2 * i] + act[2 * i + 1] == 0) continue;
+      // (an odd iteration still runs: it replaces the runs marked on the even one before it)
+      if (act[2 * i] + act[2 * i + 1] == 0 && (it & 1) == 0) continue;
       rc = enqueue_iter(b, it, st);
       if (rc != CBS_OK) break;
       CBS_HIP(hipMemcpyAsync(hna, b.sc.n_active, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1076,7 +1109,8 @@ static int32_t run_profiled(std::vector<BicgSolve*>& solves, hipStream_t st, int
       act[2 * i + 1] = hna[1];
       any += hna[0] + hna[1];
     }
-    if (any == 0) break;
+    // runs marked on an even iteration are replaced on the odd one: stop after an odd one
+    if (any == 0 && (it & 1)) break;
   }
   for (auto* b : solves) {
     hipEvent_t evs[4] = {b->hi.ev0, b->hi.ev1, b->lo.ev0, b->lo.ev1};

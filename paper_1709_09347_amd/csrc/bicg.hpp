@@ -40,6 +40,8 @@ struct BicgScal {
   int32_t* conv;      // phase change this iteration: 1 widen to complex128, 2 narrow to complex64
   int32_t* ru_it;     // iteration of the last replacement (complex64 stagnation guard)
   int32_t* nrestart;  // complex64 -> complex128 restarts of the run
+  int32_t* ru_par;    // parity of the iteration that marked the run for replacement (where its
+                      // latest search direction is)
   int32_t* n_active;  // [3]: active runs in the complex64 / complex128 phase; runs marked
                       // for residual replacement
   int32_t* list;      // [3][nruns]: the runs of each of those sets, ascending (n_active entries)
