@@ -475,8 +475,10 @@ __global__ void __launch_bounds__(256) k_s2(BicgScal sc, int32_t nruns, int32_t 
   if (conv || bad || it >= max_iter || cur < sc.ru_thr[run] || stalled || diverged) {
     sc.status[run] = (st == ST_ACT_LO) ? ST_RU_LO : ST_RU_HI;
     sc.ru_par[run] = parity & 1;
-  } else if (st == ST_ACT_HI && narrow_tol > 0.0 && sc.ru_thr[run] >= 0.0 && fmax(rr, rrt) < narrow_tol) {
-    // the residual is small enough for complex64 vectors and operator applications
+  } else if (st == ST_ACT_HI && narrow_tol > 0.0 && sc.ru_thr[run] >= 0.0 && fmax(rr, rrt) < narrow_tol &&
+             (parity & 1)) {
+    // the residual is small enough for complex64 vectors and operator applications (on odd
+    // iterations, where k_phase runs)
     sc.status[run] = ST_ACT_LO;
     sc.conv[run] = 2;
     sc.ru_it[run] = it;
@@ -1048,13 +1050,15 @@ static int32_t enqueue_iter(BicgSolve& b, int parity, hipStream_t st) {
   // direction to that iteration's buffer (k_ru_pre).  Chunks of iterations are even, so
   // every chunk ends with a replacement.
   if (parity & 1) CBS_TRY(enqueue_replacement(b, parity, st));
-  if (b.mixed) {
+  // phase changes (narrowing in k_s2, restarts in k_s3) and the work queue (items finished in
+  // k_s3) come about on odd iterations only, so their launches are kept to those
+  if (b.mixed && (parity & 1)) {
     hipLaunchKernelGGL(k_phase, dim3(grid8(nl)), dim3(256), 0, st, s->N, b.nchunks, nl, (const int32_t*)b.sc.conv,
                        (const Pair<double>*)b.hi.R, b.hi.Pb[parity & 1], b.hi.X, b.lo.R, b.lo.Pb[parity & 1],
                        b.lo.X, b.Y);
     CBS_HIP(hipGetLastError());
   }
-  if (b.q != nullptr) CBS_TRY(enqueue_queue_step(b, st, true));
+  if (b.q != nullptr && (parity & 1)) CBS_TRY(enqueue_queue_step(b, st, true));
   return CBS_OK;
 }
 
